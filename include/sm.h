@@ -1,0 +1,152 @@
+/*
+ * sm.h -- C ABI of the exact cone-beam system-matrix library (MI355X, HIP).
+ *
+ * The library applies the system matrix W of Simbrunner, Krenn, Zach and
+ * Habring, "Computation of a Consistent System Matrix for Cone-beam Computed
+ * Tomography" (arXiv 2511.12235), without storing it.  W maps a voxel image u
+ * to the measurements p = W u (Sec. I, eq. "ip"); its entry W_ij is the exact
+ * measure (area in 2D, volume in 3D, in absolute units mm^2 / mm^3) of the
+ * part of voxel j inside the beam of detector element i, so that W u equals
+ * the beam-integrated attenuation of a piecewise-constant object exactly (the
+ * "consistency" definition of Sec. I).
+ *
+ * Geometry (Sec. III-A, eq. "z rotation"; appendix "Fundamental relations"):
+ * the source sits at (s cos(phi), s sin(phi), 0) and rotates about +z; the
+ * flat detector is perpendicular to the central ray at distance d beyond the
+ * origin (source-detector distance D = s + d).  A point p has depth
+ * l = s - (x cos(phi) + y sin(phi)) and detector coordinates u = D t / l,
+ * v = D z / l with t = y cos(phi) - x sin(phi).  Detector column m_y spans
+ * [det_y0 + m_y dy, det_y0 + (m_y + 1) dy] in u, row m_z spans
+ * [det_z0 + m_z dz, det_z0 + (m_z + 1) dz] in v.  Voxel (ix, iy, iz) spans
+ * [x0 + ix a, x0 + (ix + 1) a] x [y0 + iy b, ...] x [z0 + iz c, ...].
+ *
+ * Conventions shared by every entry point:
+ *  - Layouts (C order, last index fastest):
+ *      volume    x[B][nz][ny][nx]            (voxel j = (iz ny + iy) nx + ix)
+ *      sinogram  y[B][n_p][det_nz][det_ny]   (ray i = (view det_nz + m_z) det_ny + m_y)
+ *    In 2D nz = det_nz = 1.  The element type is float for SM_FP32 plans and
+ *    double for SM_FP64 plans.
+ *  - Device pointers are HIP device memory owned by the caller.  Host
+ *    pointers are named *_host.  The plan owns only its own tables.
+ *  - Every call returns an sm_status and never throws or aborts.  On a
+ *    non-OK status the outputs are unspecified and sm_last_error() holds a
+ *    message (thread-local).
+ *  - sm_forward / sm_back are stream-ordered on the given hipStream_t (NULL =
+ *    the default stream); they never allocate, never synchronise and overwrite
+ *    their output (no zero-initialisation needed).  A plan is immutable after
+ *    creation and may be used concurrently from several host threads and
+ *    streams, provided each concurrent call has its own workspace.
+ */
+#ifndef SM_H
+#define SM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SM_OK = 0,
+    SM_EINVAL = 1,       /* bad argument or geometry */
+    SM_ENOMEM = 2,       /* device or host allocation failed */
+    SM_EDEVICE = 3,      /* HIP runtime error (launch, copy) */
+    SM_EUNSUPPORTED = 4, /* valid request outside the implemented envelope */
+    SM_ERANGE = 5        /* caller buffer too small (see sm_weights_csr) */
+} sm_status;
+
+typedef enum { SM_FP32 = 0, SM_FP64 = 1 } sm_precision;
+
+/* Scanner and grid description (plain data, copied by sm_plan_create).
+ * NaN in x0/y0/z0 selects the grid centred on the rotation axis
+ * (x0 = -nx a / 2, ...); NaN in det_y0/det_z0 selects the centred detector
+ * (det_y0 = -det_ny dy / 2, ...).  phi == NULL selects phi_k = 2 pi k / n_p
+ * (equidistant in [0, 2 pi), Sec. IV).  trig, when non-NULL, supplies the
+ * exact (cos(phi_k), sin(phi_k)) pairs and takes precedence over phi. */
+typedef struct {
+    int32_t dim;              /* 2 (fan beam) or 3 (cone beam) */
+    int32_t nx, ny, nz;       /* voxels per axis; nz == 1 in 2D */
+    double a, b, c;           /* voxel side lengths; c ignored in 2D */
+    double x0, y0, z0;        /* grid minimum corner (NaN = centred) */
+    int32_t n_p;              /* number of projection angles */
+    int32_t reserved0;        /* must be 0 */
+    const double *phi;        /* host array of n_p angles (radians) or NULL */
+    const double *trig;       /* host array of n_p (cos, sin) pairs or NULL */
+    double s;                 /* source-to-origin distance, s > 0 */
+    double d;                 /* origin-to-detector distance, s + d > 0 */
+    int32_t det_ny, det_nz;   /* detector columns (u) and rows (v); det_nz == 1 in 2D */
+    double dy, dz;            /* detector element side lengths; dz ignored in 2D */
+    double det_y0, det_z0;    /* first detector corner (NaN = centred) */
+} sm_geometry;
+
+typedef struct sm_plan sm_plan;
+
+/* Validate the geometry and build the per-view tables on the current HIP
+ * device (Sec. III-A).  Rejects (SM_EINVAL) non-positive sizes or pitches,
+ * dim not in {2, 3}, non-finite values, and any view in which a grid corner
+ * has depth l <= 0 (source inside or behind the grid).  Returns
+ * SM_EUNSUPPORTED for det_nz > 1024 in 3D.  The plan must be destroyed with
+ * sm_plan_destroy on the same device. */
+sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan **out);
+
+/* Release the plan and its device tables.  NULL is accepted. */
+sm_status sm_plan_destroy(sm_plan *plan);
+
+/* Problem sizes: number of voxels N, number of measurements M = N_d N_p
+ * (Sec. I), and the workspace bytes that sm_forward / sm_back need per batch
+ * element (multiply by the batch).  Any output pointer may be NULL. */
+sm_status sm_plan_sizes(const sm_plan *plan, int64_t *n_vox, int64_t *n_rays,
+                        int64_t *ws_bytes_per_batch);
+
+/* Forward projection y = W x (Sec. III-B Algorithm 1 for 2D; Sec. III-C for
+ * 3D), for `batch` volumes of the plan's geometry: x[batch][nz][ny][nx] in,
+ * y[batch][n_p][det_nz][det_ny] out (overwritten).  ws is a device workspace
+ * of at least batch * ws_bytes_per_batch bytes (may be NULL when that is 0).
+ * Weights are recomputed on the fly; each is evaluated once per call and
+ * applied to every batch element. */
+sm_status sm_forward(const sm_plan *plan, const void *x, void *y, int32_t batch, void *ws,
+                     int64_t ws_bytes, void *hip_stream);
+
+/* Adjoint (back projection) x = W^T y with the same weights as sm_forward
+ * (the matched pair whose adjoint mismatch Sec. IV reports).  Layouts and
+ * workspace rules as sm_forward; x is overwritten. */
+sm_status sm_back(const sm_plan *plan, const void *y, void *x, int32_t batch, void *ws,
+                  int64_t ws_bytes, void *hip_stream);
+
+/* The explicit matrix W in CSR form (Sec. I: W in R^{M x N}) for small
+ * problems, written to host arrays.  Entries with W_ij <= tau_keep =
+ * 1e-12 * (voxel measure) are treated as exact zeros; the pattern is decided
+ * in FP64 whatever the value precision.  Rows are ordered by measurement
+ * index, columns ascending within a row.
+ * Two-call protocol: with row_ptr_host == NULL only *nnz_inout is written
+ * (the number of entries).  Otherwise row_ptr_host must hold M + 1 int64,
+ * col_idx_host and val_host (float for SM_FP32 values, double for SM_FP64)
+ * *nnz_inout entries; SM_ERANGE is returned when *nnz_inout is too small.
+ * The counting call works at any size (it is how the number of nonzero
+ * voxel-detector pairs is obtained); filling is limited to 4e8 entries and
+ * 2^31 - 1 voxels (SM_EUNSUPPORTED beyond).  Synchronises the current device. */
+sm_status sm_weights_csr(const sm_plan *plan, sm_precision values, int64_t *nnz_inout,
+                         int64_t *row_ptr_host, int32_t *col_idx_host, void *val_host);
+
+/* Footprint boxes of every voxel in one view (eq. "relevant detectors 2d"
+ * and the row bounds of Sec. III-C, with strict inequalities): for voxel j,
+ * boxes_host[4 j + 0..3] = first column, last column, first row, last row of
+ * the detector elements whose open cell meets the open detector-coordinate
+ * range of the voxel (first > last when empty).  The box is computed in FP64
+ * from the corners with the fixed operation order l = s - (x cos + y sin),
+ * t = y cos - x sin, u = (D t) / l, v = (D z) / l (no fused multiply-add),
+ * x = x0 + ix a etc., and cell edges det_y0 + m dy.  Host output of
+ * nx*ny*nz*4 int32.  Synchronises the current device. */
+sm_status sm_footprints(const sm_plan *plan, int32_t view, int32_t *boxes_host);
+
+/* Static text for a status code. */
+const char *sm_status_str(sm_status status);
+
+/* Message describing the last non-OK status returned on this host thread. */
+const char *sm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SM_H */

@@ -67,6 +67,8 @@ def lib():
         L.orc_forward.argtypes = [G, dp, ip32, C.c_int, C.c_double, dp]
         L.orc_back.restype = C.c_int
         L.orc_back.argtypes = [G, dp, ip64, C.c_int64, C.c_double, dp]
+        L.orc_forward_rays.restype = C.c_int
+        L.orc_forward_rays.argtypes = [G, dp, ip64, C.c_int64, C.c_double, dp]
         L.orc_num_threads.restype = C.c_int
         _LIB = L
     return _LIB
@@ -208,3 +210,18 @@ def back(g, y, voxels=None, tau=None) -> np.ndarray:
     if L.orc_back(b.ref, _ptr(y), _ptr(vox, C.c_int64), len(vox), tau, _ptr(x)) != 0:
         raise ValueError("invalid geometry: source inside or behind the grid")
     return x.reshape(g.vol_shape) if full else x
+
+
+def forward_rays(g, x, rays, tau=None) -> np.ndarray:
+    """y_i for the listed linear ray indices (brute force over all voxels)."""
+    L = lib()
+    b = _Bound(g)
+    tau = default_tau(g) if tau is None else float(tau)
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+    if x.size != g.n_vox:
+        raise ValueError("x has the wrong size")
+    rays = np.ascontiguousarray(np.asarray(rays, dtype=np.int64))
+    y = np.empty(len(rays), dtype=np.float64)
+    if L.orc_forward_rays(b.ref, _ptr(x), _ptr(rays, C.c_int64), len(rays), tau, _ptr(y)) != 0:
+        raise ValueError("invalid geometry: source inside or behind the grid")
+    return y

@@ -629,6 +629,38 @@ int orc_back(const orc_geom *g, const double *y, const int64_t *vox, int64_t n_s
     return bad ? -1 : 0;
 }
 
+/* y_i = sum_j W_ij x_j for a list of rays i (brute force over all voxels:
+ * every voxel whose footprint box holds the element is clipped).  Parallel
+ * over rays; each ray is summed serially in voxel order.                  */
+int orc_forward_rays(const orc_geom *g, const double *x, const int64_t *rays, int64_t n_sel,
+                     double tau, double *y)
+{
+    int bad = 0;
+    const int64_t per = (int64_t)g->det_nz * g->det_ny;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < n_sel; ++q) {
+        const int64_t i = rays[q];
+        const int view = (int)(i / per);
+        const int r = (int)((i % per) / g->det_ny);
+        const int k = (int)(i % g->det_ny);
+        double cp, sp;
+        view_trig(g, view, &cp, &sp);
+        double acc = 0.0;
+        for (int iz = 0; iz < g->nz; ++iz)
+            for (int iy = 0; iy < g->ny; ++iy)
+                for (int ix = 0; ix < g->nx; ++ix) {
+                    int box[4];
+                    int st = footprint(g, cp, sp, ix, iy, iz, box);
+                    if (st < 0) { bad = 1; continue; }
+                    if (st == 0 || k < box[0] || k > box[1] || r < box[2] || r > box[3]) continue;
+                    double w = cell_measure_c(g, cp, sp, ix, iy, iz, k, r);
+                    if (w > tau) acc += w * x[((int64_t)iz * g->ny + iy) * g->nx + ix];
+                }
+        y[q] = acc;
+    }
+    return bad ? -1 : 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -1,0 +1,168 @@
+"""Torch front end of the HIP system-matrix library.
+
+``SystemMatrix`` owns one plan (include/sm.h) and applies W (forward
+projection, Sec. III of arXiv 2511.12235) and W^T (its exact adjoint) to
+device tensors through the C ABI.  Tensors are validated here; all
+arithmetic runs in the library's kernels on the caller's current HIP stream.
+``Projection`` wraps the pair as a ``torch.autograd.Function``: W is linear,
+so the backward of y = W x is W^T applied to the incoming gradient.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _dtype_of(precision: str):
+    if precision == "fp32":
+        return torch.float32, _lib.SM_FP32
+    if precision == "fp64":
+        return torch.float64, _lib.SM_FP64
+    raise ValueError("precision must be 'fp32' or 'fp64'")
+
+
+class SystemMatrix:
+    """Matrix-free exact system matrix W for one scan geometry.
+
+    ``geometry`` has the attributes of ``workloads.Geometry``.  Volumes are
+    tensors of shape (nz, ny, nx) or (B, nz, ny, nx), sinograms (n_p, det_nz,
+    det_ny) or (B, n_p, det_nz, det_ny), on the plan's device, contiguous, in
+    the plan's dtype.
+    """
+
+    def __init__(self, geometry, precision: str = "fp32", device=None):
+        self.geometry = geometry
+        self.precision = precision
+        self.dtype, prec = _dtype_of(precision)
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else
+                           torch.device(device).index or 0)
+        self.device = dev
+        L = _lib.lib()
+        keep = []
+        gs = _lib.make_geometry_struct(geometry, keep)
+        plan = C.c_void_p()
+        with torch.cuda.device(dev):
+            _lib.check(L.sm_plan_create(C.byref(gs), prec, C.byref(plan)), "sm_plan_create")
+        self._plan = plan
+        nv, nr, ws = C.c_int64(), C.c_int64(), C.c_int64()
+        _lib.check(L.sm_plan_sizes(plan, C.byref(nv), C.byref(nr), C.byref(ws)), "sm_plan_sizes")
+        self.n_vox, self.n_rays, self.ws_per_batch = nv.value, nr.value, ws.value
+        self.vol_shape = (geometry.nz, geometry.ny, geometry.nx)
+        self.sino_shape = (geometry.n_p, geometry.det_nz, geometry.det_ny)
+
+    # ------------------------------------------------------------------ utils
+    def close(self):
+        if getattr(self, "_plan", None):
+            _lib.lib().sm_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, t: torch.Tensor, shape, name: str) -> int:
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch.Tensor" % name)
+        if t.device != self.device:
+            raise ValueError("%s is on %s, the plan on %s" % (name, t.device, self.device))
+        if t.dtype != self.dtype:
+            raise TypeError("%s has dtype %s, the plan needs %s" % (name, t.dtype, self.dtype))
+        if not t.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if tuple(t.shape) == tuple(shape):
+            return 1
+        if t.dim() == len(shape) + 1 and tuple(t.shape[1:]) == tuple(shape):
+            return t.shape[0]
+        raise ValueError("%s has shape %s, expected %s or (B, *%s)" % (name, tuple(t.shape), shape, shape))
+
+    def workspace(self, batch: int) -> torch.Tensor:
+        return torch.empty(max(self.ws_per_batch * batch, 1), dtype=torch.uint8, device=self.device)
+
+    # -------------------------------------------------------------- operators
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None,
+                ws: torch.Tensor | None = None) -> torch.Tensor:
+        """y = W x on the current stream."""
+        B = self._check(x, self.vol_shape, "x")
+        batched = x.dim() == 4
+        shape = ((B,) if batched else ()) + self.sino_shape
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=self.device)
+        elif self._check(out, self.sino_shape, "out") != B:
+            raise ValueError("out batch does not match x")
+        if ws is None:
+            ws = self.workspace(B)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().sm_forward(self._plan, x.data_ptr(), out.data_ptr(), B, ws.data_ptr(),
+                                         ws.numel(), st), "sm_forward")
+        return out
+
+    def back(self, y: torch.Tensor, out: torch.Tensor | None = None,
+             ws: torch.Tensor | None = None) -> torch.Tensor:
+        """x = W^T y on the current stream."""
+        B = self._check(y, self.sino_shape, "y")
+        batched = y.dim() == 4
+        shape = ((B,) if batched else ()) + self.vol_shape
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=self.device)
+        elif self._check(out, self.vol_shape, "out") != B:
+            raise ValueError("out batch does not match y")
+        if ws is None:
+            ws = self.workspace(B)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().sm_back(self._plan, y.data_ptr(), out.data_ptr(), B, ws.data_ptr(),
+                                      ws.numel(), st), "sm_back")
+        return out
+
+    __matmul__ = forward
+
+    def weights_csr(self, values: str | None = None):
+        """(row_ptr int64 [M+1], col_idx int32 [nnz], values [nnz]) on the host;
+        the pattern is decided in FP64 (entries <= 1e-12 voxel measure drop)."""
+        vprec = self.precision if values is None else values
+        vdt, vcode = (np.float32, _lib.SM_FP32) if vprec == "fp32" else (np.float64, _lib.SM_FP64)
+        L = _lib.lib()
+        nnz = C.c_int64(0)
+        with torch.cuda.device(self.device):
+            _lib.check(L.sm_weights_csr(self._plan, vcode, C.byref(nnz), None, None, None),
+                       "sm_weights_csr")
+            row_ptr = np.empty(self.n_rays + 1, dtype=np.int64)
+            cols = np.empty(max(nnz.value, 1), dtype=np.int32)
+            vals = np.empty(max(nnz.value, 1), dtype=vdt)
+            _lib.check(L.sm_weights_csr(self._plan, vcode, C.byref(nnz),
+                                        row_ptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                                        cols.ctypes.data_as(C.POINTER(C.c_int32)),
+                                        vals.ctypes.data_as(C.c_void_p)), "sm_weights_csr")
+        n = nnz.value
+        return row_ptr, cols[:n], vals[:n]
+
+    def footprints(self, view: int) -> np.ndarray:
+        """int32 [nz, ny, nx, 4] footprint boxes of one view."""
+        out = np.empty(self.vol_shape + (4,), dtype=np.int32)
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.lib().sm_footprints(self._plan, int(view),
+                                                out.ctypes.data_as(C.POINTER(C.c_int32))),
+                       "sm_footprints")
+        return out
+
+
+class Projection(torch.autograd.Function):
+    """y = W x with dL/dx = W^T dL/dy."""
+
+    @staticmethod
+    def forward(ctx, x, A: SystemMatrix):
+        ctx.A = A
+        return A.forward(x.contiguous())
+
+    @staticmethod
+    def backward(ctx, gy):
+        return ctx.A.back(gy.contiguous()), None
+
+
+def project(x: torch.Tensor, A: SystemMatrix) -> torch.Tensor:
+    return Projection.apply(x, A)

@@ -1,0 +1,183 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: FP64 plans within 1e-12 relative L2 of the oracle, FP32 plans within
+1e-5; footprint boxes and the CSR pattern bit-exact; dot-product test at
+1e-12 (FP64) / 1e-6 (FP32).  Small geometries are compared in full; the
+256^3 and 128^3 cone-beam workloads are compared on sampled rays and voxels
+that the oracle computes one by one, plus the row-sum invariant.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2511_12235_amd import workloads as wl
+from paper_2511_12235_amd.projector import SystemMatrix
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _t(a, prec):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, torch.float64 if prec == "fp64" else torch.float32)
+
+
+def _say(*msg):
+    print("[case]", *msg, flush=True)
+
+
+DEG_TRIG = np.array([[1.0, 0.0], [0.0, 1.0], [-1.0, 0.0], [0.0, -1.0],
+                     [np.cos(1e-9), np.sin(1e-9)], [np.cos(np.pi / 2 + 1e-7), np.sin(np.pi / 2 + 1e-7)],
+                     [np.cos(np.pi / 4), np.sin(np.pi / 4)], [np.cos(2.2), np.sin(2.2)]])
+
+
+def geometries():
+    g = {}
+    g["c1_fan64"] = wl.c1_fan2d()
+    g["fan_odd"] = wl.make_geometry(2, (37, 29), (1.1, 0.9), 23, 80.0, 60.0, (51,), (1.7,),
+                                    det_corner=(-40.0, 0.0))
+    g["cone_small"] = wl.scaled(wl.c2_cone128(), (26, 22, 20), (30, 26), 12)
+    g["cone_degenerate"] = wl.make_geometry(3, (12, 11, 10), (1.0, 1.0, 1.0), len(DEG_TRIG), 40.0, 30.0,
+                                            (20, 18), (1.2, 1.1), trig=DEG_TRIG,
+                                            phi=np.arctan2(DEG_TRIG[:, 1], DEG_TRIG[:, 0]))
+    g["cone_aniso_offset"] = wl.make_geometry(3, (17, 13, 70), (0.7, 1.3, 0.45), 9, 35.0, 25.0,
+                                              (29, 83), (0.9, 0.5),
+                                              det_corner=(-11.0, -20.0), corner=(-5.0, -9.0, -14.0))
+    return g
+
+
+GEOMS = geometries()
+SMALL = list(GEOMS)
+
+
+@pytest.fixture(scope="module")
+def oracle_mats():
+    return {}
+
+
+def _W(name, cache):
+    if name not in cache:
+        cache[name] = O.matrix(GEOMS[name])
+    return cache[name]
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forward_adjoint_match_oracle(name, prec, oracle_mats):
+    g = GEOMS[name]
+    _say("forward/adjoint", name, prec)
+    W = _W(name, oracle_mats)
+    A = SystemMatrix(g, prec, device=DEV)
+    x = wl.ellipse_phantom(g, 5, seed=0) + 0.1 * wl.uniform(g.vol_shape, 1)
+    y = wl.uniform(g.sino_shape, 2)
+    yg = A.forward(_t(x, prec)).cpu().numpy()
+    xg = A.back(_t(y, prec)).cpu().numpy()
+    torch.cuda.synchronize()
+    assert _rel(yg.ravel(), W @ x.ravel()) <= TOL[prec]
+    assert _rel(xg.ravel(), W.T @ y.ravel()) <= TOL[prec]
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_csr_pattern_and_values(name, oracle_mats):
+    g = GEOMS[name]
+    _say("csr", name)
+    W = _W(name, oracle_mats)
+    A = SystemMatrix(g, "fp64", device=DEV)
+    rp, ci, va = A.weights_csr("fp64")
+    assert np.array_equal(rp, W.indptr.astype(np.int64))
+    assert np.array_equal(ci, W.indices.astype(np.int32))
+    assert _rel(va, W.data) <= 1e-12
+    rp32, ci32, va32 = A.weights_csr("fp32")
+    assert np.array_equal(rp32, rp) and np.array_equal(ci32, ci)
+    assert _rel(va32, W.data) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["c1_fan64", "cone_small", "cone_degenerate", "cone_aniso_offset"])
+def test_footprints_bit_exact(name):
+    g = GEOMS[name]
+    _say("footprints", name)
+    A = SystemMatrix(g, "fp32", device=DEV)
+    for v in sorted({0, 1, g.n_p // 2, g.n_p - 1}):
+        assert np.array_equal(A.footprints(v), O.footprints(g, v)), v
+
+
+@pytest.mark.parametrize("name", ["fan_odd", "cone_small", "cone_aniso_offset"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dot_product(name, prec):
+    g = GEOMS[name]
+    _say("dot", name, prec)
+    A = SystemMatrix(g, prec, device=DEV)
+    x = wl.random_unit(g.vol_shape, 5)
+    y = wl.random_unit(g.sino_shape, 6)
+    Wx = A.forward(_t(x, prec)).double().cpu().numpy()
+    Wty = A.back(_t(y, prec)).double().cpu().numpy()
+    lhs, rhs = float(np.vdot(Wx, y)), float(np.vdot(x, Wty))
+    bound = 1e-12 if prec == "fp64" else 1e-6
+    assert abs(lhs - rhs) <= bound * np.linalg.norm(Wx) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("name", ["fan_odd", "cone_small"])
+@pytest.mark.parametrize("batch", [3, 8, 11])
+def test_batched_equals_single(name, batch):
+    g = GEOMS[name]
+    _say("batch", name, batch)
+    A = SystemMatrix(g, "fp32", device=DEV)
+    X = np.stack([wl.ellipse_phantom(g, 4, seed=10 + i) for i in range(batch)])
+    Y = np.stack([wl.uniform(g.sino_shape, 20 + i) for i in range(batch)])
+    yb = A.forward(_t(X, "fp32")).cpu().numpy()
+    xb = A.back(_t(Y, "fp32")).cpu().numpy()
+    for i in range(batch):
+        assert np.array_equal(yb[i], A.forward(_t(X[i], "fp32")).cpu().numpy())
+        assert np.array_equal(xb[i], A.back(_t(Y[i], "fp32")).cpu().numpy())
+
+
+def test_deterministic_repeat():
+    g = GEOMS["cone_small"]
+    _say("determinism")
+    A = SystemMatrix(g, "fp32", device=DEV)
+    x = _t(wl.ellipse_phantom(g, 5, seed=3), "fp32")
+    y = _t(wl.uniform(g.sino_shape, 4), "fp32")
+    assert torch.equal(A.forward(x), A.forward(x))
+    assert torch.equal(A.back(y), A.back(y))
+
+
+@pytest.mark.parametrize("which", ["c2_cone128", "c3_cone256"])
+def test_full_size_sampled(which):
+    """Full-size workloads in the launch configuration the benchmark times:
+    sampled rays (brute force in the oracle), sampled voxels, and the row
+    sums W 1 against one clip of the whole grid box per ray."""
+    g = getattr(wl, which)()
+    _say("full size", which)
+    rng = np.random.default_rng(7)
+    A = SystemMatrix(g, "fp32", device=DEV)
+    x = wl.ellipse_phantom(g, 10, seed=1 if which == "c2_cone128" else 2)
+    y = A.forward(_t(x, "fp32")).cpu().numpy().ravel()
+    n_rays = 24 if which == "c3_cone256" else 48
+    rays = rng.choice(g.n_rays, size=n_rays, replace=False)
+    # rays near the central row and on the degenerate views are included
+    views = np.array([0, g.n_p // 4, g.n_p // 2])
+    extra = (views * g.det_nz + g.det_nz // 2) * g.det_ny + g.det_ny // 2
+    rays = np.concatenate([rays, extra])
+    yo = O.forward_rays(g, x, rays)
+    assert _rel(y[rays], yo) <= 1e-5
+    # row sums of W against the grid-box clip
+    ones = A.forward(torch.ones(g.vol_shape, device=DEV)).cpu().numpy().ravel()
+    gb = []
+    for i in rays[:16]:
+        v, rem = divmod(int(i), g.det_nz * g.det_ny)
+        r, k = divmod(rem, g.det_ny)
+        gb.append(O.ray_gridbox(g, v, k, r))
+    assert _rel(ones[rays[:16]], gb) <= 1e-5
+    # adjoint on sampled voxels
+    ys = wl.uniform(g.sino_shape, 9)
+    xb = A.back(_t(ys, "fp32")).cpu().numpy().ravel()
+    vox = rng.choice(g.n_vox, size=48, replace=False)
+    xo = O.back(g, ys, vox)
+    assert _rel(xb[vox], xo) <= 1e-5
