@@ -173,16 +173,20 @@ __device__ void voxel_view_weights(const DevGeom &G, int view, int ix, int iy, i
     }
 }
 
+// Grid-stride loops: an AMD dispatch holds at most 2^32 work-items per
+// dimension, and n_p * n_vox exceeds that for the larger scans.
 __global__ void csr_count_kernel(DevGeom G, double tau_keep, int32_t *row_cnt)
 {
     const int64_t nvox = (int64_t)G.nx * G.ny * G.nz;
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nvox * G.n_p) return;
-    const int view = (int)(q / nvox);
-    const int64_t j = q - (int64_t)view * nvox;
-    const int ix = (int)(j % G.nx), iy = (int)((j / G.nx) % G.ny), iz = (int)(j / ((int64_t)G.nx * G.ny));
-    voxel_view_weights(G, view, ix, iy, iz, tau_keep, false,
-                       [&](int64_t i, double, float) { atomicAdd(&row_cnt[i], 1); });
+    const int64_t n = nvox * G.n_p;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int view = (int)(q / nvox);
+        const int64_t j = q - (int64_t)view * nvox;
+        const int ix = (int)(j % G.nx), iy = (int)((j / G.nx) % G.ny), iz = (int)(j / ((int64_t)G.nx * G.ny));
+        voxel_view_weights(G, view, ix, iy, iz, tau_keep, false,
+                           [&](int64_t i, double, float) { atomicAdd(&row_cnt[i], 1); });
+    }
 }
 
 template <typename V>
@@ -190,36 +194,39 @@ __global__ void csr_fill_kernel(DevGeom G, double tau_keep, const int64_t *row_p
                                 int32_t *cursor, int32_t *cols, V *vals)
 {
     const int64_t nvox = (int64_t)G.nx * G.ny * G.nz;
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nvox * G.n_p) return;
-    const int view = (int)(q / nvox);
-    const int64_t j = q - (int64_t)view * nvox;
-    const int ix = (int)(j % G.nx), iy = (int)((j / G.nx) % G.ny), iz = (int)(j / ((int64_t)G.nx * G.ny));
+    const int64_t n = nvox * G.n_p;
     const bool want32 = sizeof(V) == 4;
-    voxel_view_weights(G, view, ix, iy, iz, tau_keep, want32, [&](int64_t i, double w, float w32) {
-        const int64_t pos = row_ptr[i] + atomicAdd(&cursor[i], 1);
-        cols[pos] = (int32_t)j;
-        vals[pos] = want32 ? (V)w32 : (V)w;
-    });
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int view = (int)(q / nvox);
+        const int64_t j = q - (int64_t)view * nvox;
+        const int ix = (int)(j % G.nx), iy = (int)((j / G.nx) % G.ny), iz = (int)(j / ((int64_t)G.nx * G.ny));
+        voxel_view_weights(G, view, ix, iy, iz, tau_keep, want32, [&](int64_t i, double w, float w32) {
+            const int64_t pos = row_ptr[i] + atomicAdd(&cursor[i], 1);
+            cols[pos] = (int32_t)j;
+            vals[pos] = want32 ? (V)w32 : (V)w;
+        });
+    }
 }
 
 template <typename V>
 __global__ void csr_sort_kernel(const int64_t *row_ptr, int64_t n_rows, int32_t *cols, V *vals)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_rows) return;
-    const int64_t a = row_ptr[i], e = row_ptr[i + 1];
-    for (int64_t p = a + 1; p < e; ++p) {
-        const int32_t c = cols[p];
-        const V v = vals[p];
-        int64_t q = p - 1;
-        while (q >= a && cols[q] > c) {
-            cols[q + 1] = cols[q];
-            vals[q + 1] = vals[q];
-            --q;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = row_ptr[i], e = row_ptr[i + 1];
+        for (int64_t p = a + 1; p < e; ++p) {
+            const int32_t c = cols[p];
+            const V v = vals[p];
+            int64_t q = p - 1;
+            while (q >= a && cols[q] > c) {
+                cols[q + 1] = cols[q];
+                vals[q + 1] = vals[q];
+                --q;
+            }
+            cols[q + 1] = c;
+            vals[q + 1] = v;
         }
-        cols[q + 1] = c;
-        vals[q + 1] = v;
     }
 }
 
@@ -251,11 +258,17 @@ __global__ void __launch_bounds__(1024) scan_kernel(const int32_t *cnt, int64_t 
     }
 }
 
+static dim3 stride_grid(int64_t n, int threads)
+{
+    const int64_t want = (n + threads - 1) / threads;
+    return dim3((unsigned)(want < (1 << 20) ? (want > 0 ? want : 1) : (1 << 20)));
+}
+
 hipError_t launch_csr_count(const DevGeom &G, double tau_keep, int32_t *row_cnt, hipStream_t st)
 {
     const int64_t n = (int64_t)G.nx * G.ny * G.nz * G.n_p;
-    hipLaunchKernelGGL(csr_count_kernel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, G,
-                       tau_keep, row_cnt);
+    hipLaunchKernelGGL(csr_count_kernel, stride_grid(n, 128), dim3(128), 0, st, G, tau_keep,
+                       row_cnt);
     return hipGetLastError();
 }
 
@@ -264,7 +277,7 @@ hipError_t launch_csr_fill(const DevGeom &G, bool fp64_vals, double tau_keep,
                            hipStream_t st)
 {
     const int64_t n = (int64_t)G.nx * G.ny * G.nz * G.n_p;
-    const dim3 grid((unsigned)((n + 127) / 128));
+    const dim3 grid = stride_grid(n, 128);
     if (fp64_vals)
         hipLaunchKernelGGL(csr_fill_kernel<double>, grid, dim3(128), 0, st, G, tau_keep, row_ptr,
                            cursor, cols, (double *)vals);
@@ -277,7 +290,7 @@ hipError_t launch_csr_fill(const DevGeom &G, bool fp64_vals, double tau_keep,
 hipError_t launch_csr_sort(const int64_t *row_ptr, int64_t n_rows, int32_t *cols, void *vals,
                            bool fp64_vals, hipStream_t st)
 {
-    const dim3 grid((unsigned)((n_rows + 127) / 128));
+    const dim3 grid = stride_grid(n_rows, 128);
     if (fp64_vals)
         hipLaunchKernelGGL(csr_sort_kernel<double>, grid, dim3(128), 0, st, row_ptr, n_rows, cols,
                            (double *)vals);

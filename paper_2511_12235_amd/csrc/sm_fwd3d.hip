@@ -237,12 +237,15 @@ template <typename T, int NBAT>
 static size_t fwd3d_lds(const DevGeom &G, const LaunchCfg &L, int &NB)
 {
     const int nthr = L.fwd_threads;
-    // pixels per pass: keep the staged columns near 32 KiB
+    // pixels per pass: staged columns near 32 KiB, records + columns within budget
+    const size_t fixed = sizeof(int) * (2 * (size_t)nthr + 1 + 20);
+    const size_t per_pix = sizeof(Rec<T>) + sizeof(T) * (size_t)NBAT * G.nz;
     NB = (int)(32768 / ((size_t)sizeof(T) * NBAT * G.nz));
+    const int nb_fit = L.lds_budget > (int)fixed ? (int)(((size_t)L.lds_budget - fixed) / per_pix) : 0;
+    NB = NB > nb_fit ? nb_fit : NB;
     NB = NB < 1 ? 1 : (NB > 64 ? 64 : NB);
     if (NB > nthr) NB = nthr;
-    size_t lds = sizeof(Rec<T>) * NB + sizeof(T) * (size_t)NB * NBAT * G.nz +
-                 sizeof(int) * (2 * (size_t)nthr + 1 + 20);
+    size_t lds = per_pix * NB + fixed;
     const size_t lds_end = sizeof(T) * (size_t)(2 * nthr + 2) * NBAT;  // exchange + reduction
     return lds_end > lds ? lds_end : lds;
 }
