@@ -92,16 +92,21 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
 /* Release the plan and its device tables.  NULL is accepted. */
 sm_status sm_plan_destroy(sm_plan *plan);
 
-/* Problem sizes: number of voxels N, number of measurements M = N_d N_p
- * (Sec. I), and the workspace bytes that sm_forward / sm_back need per batch
- * element (multiply by the batch).  Any output pointer may be NULL. */
-sm_status sm_plan_sizes(const sm_plan *plan, int64_t *n_vox, int64_t *n_rays,
-                        int64_t *ws_bytes_per_batch);
+/* Problem sizes: number of voxels N and number of measurements M = N_d N_p
+ * (Sec. I).  Either output pointer may be NULL. */
+sm_status sm_plan_sizes(const sm_plan *plan, int64_t *n_vox, int64_t *n_rays);
+
+/* Device workspace bytes that sm_forward / sm_back need for `batch` volumes
+ * (0 in 2D).  In 3D it holds the strip records of one chunk of views (the
+ * top-view polygons of Sec. III-B with their chord tables, about 1 GiB at
+ * most) and one FP64 column buffer per batch element. */
+sm_status sm_workspace_size(const sm_plan *plan, int32_t batch, int64_t *bytes);
 
 /* Forward projection y = W x (Sec. III-B Algorithm 1 for 2D; Sec. III-C for
  * 3D), for `batch` volumes of the plan's geometry: x[batch][nz][ny][nx] in,
  * y[batch][n_p][det_nz][det_ny] out (overwritten).  ws is a device workspace
- * of at least batch * ws_bytes_per_batch bytes (may be NULL when that is 0).
+ * of at least sm_workspace_size(batch) bytes (may be NULL when that is 0);
+ * ws_bytes is its size.
  * Weights are recomputed on the fly; each is evaluated once per call and
  * applied to every batch element. */
 sm_status sm_forward(const sm_plan *plan, const void *x, void *y, int32_t batch, void *ws,

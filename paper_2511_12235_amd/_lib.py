@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libsm.so")
 SM_OK, SM_EINVAL, SM_ENOMEM, SM_EDEVICE, SM_EUNSUPPORTED, SM_ERANGE = range(6)
 SM_FP32, SM_FP64 = 0, 1
 
-EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_forward", "sm_back",
+EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_workspace_size",
+            "sm_forward", "sm_back",
             "sm_weights_csr", "sm_footprints", "sm_status_str", "sm_last_error")
 
 
@@ -61,7 +62,9 @@ def lib():
         L.sm_plan_destroy.restype = C.c_int
         L.sm_plan_destroy.argtypes = [vp]
         L.sm_plan_sizes.restype = C.c_int
-        L.sm_plan_sizes.argtypes = [vp, i64p, i64p, i64p]
+        L.sm_plan_sizes.argtypes = [vp, i64p, i64p]
+        L.sm_workspace_size.restype = C.c_int
+        L.sm_workspace_size.argtypes = [vp, C.c_int32, i64p]
         L.sm_forward.restype = C.c_int
         L.sm_forward.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_int64, vp]
         L.sm_back.restype = C.c_int

@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(256) fwd2d_kernel(DevGeom G, const T *__restri
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int view = lb / G.nu, k = lb - view * G.nu;
-    const double2 cs = view_trig(G, view);
+    const double2 cs = G.trig[view];
     const double cp = cs.x, sp = cs.y;
     const double ulo = G.u0 + (double)k * G.du, uhi = G.u0 + (double)(k + 1) * G.du;
     const double mu0 = ulo / G.D, mu1 = uhi / G.D;
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) back2d_kernel(DevGeom G, const T *__restr
 #pragma unroll
     for (int q = 0; q < NBAT; ++q) acc[q] = T(0);
     for (int view = 0; view < G.n_p; ++view) {
-        const double2 cs = view_trig(G, view);
+        const double2 cs = G.trig[view];
         const double cp = cs.x, sp = cs.y;
         int k0, k1;
         pixel_columns(G, cp, sp, ix, iy, k0, k1);

@@ -21,10 +21,14 @@ struct sm_plan {
     sm_precision prec;
     DevGeom G;
     LaunchCfg L;
+    smk::RecLayout RL;  // workspace layout of the strip records (3D)
     double2 *d_trig;
     double *d_tau;
     int64_t n_vox, n_rays;
 };
+
+// Views per record chunk: keep the records of one chunk near 1 GiB.
+static const int64_t kRecordBudget = (int64_t)1 << 30;
 
 namespace {
 
@@ -198,7 +202,6 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
     LaunchCfg &L = p->L;
     L.fwd_threads = 64 * ((G.nv + 63) / 64);
     L.back_threads = 64 * ((G.nz + 63) / 64);
-    L.back_rmax = 64;
     {
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds <= 0)
@@ -206,25 +209,29 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
         L.lds_budget = lds < 65536 ? lds : 65536;
     }
     const int tw[4] = {4, 4, 2, 2}, th[4] = {4, 2, 2, 1};
-    for (int i = 0; i < 4; ++i) {
-        L.back_tile_x[i] = tw[i];
-        L.back_tile_y[i] = th[i];
-        L.back_pcols[i] = 1;
-    }
+    for (int i = 0; i < 4; ++i) L.back_pcols[i] = 1;
+    p->RL = smk::RecLayout{};
     if (e == hipSuccess && G.dim == 3) {
         int *d_span = nullptr;
-        e = hipMalloc(&d_span, sizeof(int) * 4);
-        if (e == hipSuccess) e = hipMemset(d_span, 0, sizeof(int) * 4);
+        e = hipMalloc(&d_span, sizeof(int) * 5);
+        if (e == hipSuccess) e = hipMemset(d_span, 0, sizeof(int) * 5);
         for (int i = 0; i < 4 && e == hipSuccess; ++i) {
             const int64_t n = (int64_t)((G.nx + tw[i] - 1) / tw[i]) * ((G.ny + th[i] - 1) / th[i]) * G.n_p;
             hipLaunchKernelGGL(tile_span_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, G,
                                tw[i], th[i], d_span + i);
             e = hipGetLastError();
         }
-        int span[4] = {1, 1, 1, 1};
-        if (e == hipSuccess) e = hipMemcpy(span, d_span, sizeof(int) * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = smk::launch_strip_count(G, d_span + 4, 0);
+        int span[5] = {1, 1, 1, 1, 1};
+        if (e == hipSuccess) e = hipMemcpy(span, d_span, sizeof(int) * 5, hipMemcpyDeviceToHost);
         hipFree(d_span);
         for (int i = 0; i < 4; ++i) L.back_pcols[i] = span[i] > 0 ? span[i] : 1;
+        const int cap = span[4] > 0 ? span[4] : 1;
+        const size_t rsz = precision == SM_FP64 ? sizeof(smk::Rec<double>) : sizeof(smk::Rec<float>);
+        const int64_t per_view = (int64_t)G.nu * cap * (int64_t)rsz;
+        int64_t V = kRecordBudget / (per_view > 0 ? per_view : 1);
+        V = V < 1 ? 1 : (V > G.n_p ? G.n_p : V);
+        p->RL = smk::make_layout(cap, G.nx > G.ny ? G.nx : G.ny, (int)V, G.nu, G.nx, G.ny, rsz);
     }
     if (e != hipSuccess) {
         hipFree(p->d_trig);
@@ -245,12 +252,27 @@ sm_status sm_plan_destroy(sm_plan *p)
     return SM_OK;
 }
 
-sm_status sm_plan_sizes(const sm_plan *p, int64_t *n_vox, int64_t *n_rays, int64_t *ws)
+sm_status sm_plan_sizes(const sm_plan *p, int64_t *n_vox, int64_t *n_rays)
 {
     if (!p) return fail(SM_EINVAL, "plan is NULL");
     if (n_vox) *n_vox = p->n_vox;
     if (n_rays) *n_rays = p->n_rays;
-    if (ws) *ws = p->G.dim == 3 ? p->n_vox * (p->prec == SM_FP64 ? 8 : 4) : 0;
+    return SM_OK;
+}
+
+static int64_t workspace_bytes(const sm_plan *p, int64_t batch)
+{
+    if (p->G.dim != 3) return 0;
+    const int64_t npix = (int64_t)p->G.nx * p->G.ny;
+    return p->RL.data_off + npix * batch * (int64_t)(p->G.nz + 1) * (int64_t)sizeof(double);
+}
+
+sm_status sm_workspace_size(const sm_plan *p, int32_t batch, int64_t *bytes)
+{
+    if (!p) return fail(SM_EINVAL, "plan is NULL");
+    if (!bytes) return fail(SM_EINVAL, "bytes is NULL");
+    if (batch < 1) return fail(SM_EINVAL, "batch must be >= 1");
+    *bytes = workspace_bytes(p, batch);
     return SM_OK;
 }
 
@@ -261,7 +283,7 @@ static sm_status check_apply(const sm_plan *p, const void *in, void *out, int32_
     if (!in || !out) return fail(SM_EINVAL, "input or output pointer is NULL");
     if (batch < 1) return fail(SM_EINVAL, "batch must be >= 1");
     if (p->G.dim == 3) {
-        const int64_t need = (int64_t)batch * p->n_vox * (p->prec == SM_FP64 ? 8 : 4);
+        const int64_t need = workspace_bytes(p, batch);
         if (!ws || ws_bytes < need)
             return fail(SM_EINVAL, "workspace too small: need %lld bytes", (long long)need);
         if (p->G.ny * (int64_t)batch > 65535) return fail(SM_EUNSUPPORTED, "ny * batch > 65535");
@@ -280,8 +302,14 @@ sm_status sm_forward(const sm_plan *p, const void *x, void *y, int32_t batch, vo
     if (p->G.dim == 2) {
         e = smk::launch_fwd2d(p->G, f64, x, y, batch, st);
     } else {
-        e = smk::launch_to_columns(x, ws, f64 ? 8 : 4, batch, p->G.nz, p->G.ny, p->G.nx, st);
-        if (e == hipSuccess) e = smk::launch_fwd3d(p->G, p->L, f64, ws, y, batch, st);
+        const smk::RecLayout &RL = p->RL;
+        double *P = (double *)((char *)ws + RL.data_off);
+        e = smk::launch_prefix_columns(x, P, f64, batch, p->G.nz, p->G.ny, p->G.nx, st);
+        for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
+            const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
+            e = smk::launch_records(p->G, RL, f64, v0, nvc, ws, st);
+            if (e == hipSuccess) e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, ws, P, y, batch, st);
+        }
     }
     return e == hipSuccess ? SM_OK : hip_fail(e, "sm_forward launch");
 }
@@ -297,9 +325,17 @@ sm_status sm_back(const sm_plan *p, const void *y, void *x, int32_t batch, void 
     if (p->G.dim == 2) {
         e = smk::launch_back2d(p->G, f64, y, x, batch, st);
     } else {
-        e = smk::launch_back3d(p->G, p->L, f64, y, ws, batch, st);
+        const smk::RecLayout &RL = p->RL;
+        void *xt = (char *)ws + RL.data_off;
+        e = hipSuccess;
+        for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
+            const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
+            e = smk::launch_records(p->G, RL, f64, v0, nvc, ws, st);
+            if (e == hipSuccess)
+                e = smk::launch_back3d(p->G, p->L, RL, f64, v0, nvc, ws, y, xt, batch, v0 == 0, st);
+        }
         if (e == hipSuccess)
-            e = smk::launch_from_columns(ws, x, f64 ? 8 : 4, batch, p->G.nz, p->G.ny, p->G.nx, st);
+            e = smk::launch_from_columns(xt, x, f64 ? 8 : 4, batch, p->G.nz, p->G.ny, p->G.nx, st);
     }
     return e == hipSuccess ? SM_OK : hip_fail(e, "sm_back launch");
 }

@@ -1,5 +1,5 @@
-// sm_common.h -- device-side geometry and weight evaluation shared by the
-// forward, adjoint and CSR kernels.
+// sm_common.h -- geometry and weight evaluation shared by the record,
+// forward, adjoint and CSR kernels (device and host).
 //
 // Paper: Simbrunner, Krenn, Zach, Habring, "Computation of a Consistent
 // System Matrix for Cone-beam Computed Tomography", arXiv 2511.12235.
@@ -16,19 +16,20 @@
 // through the source t = (u_k / D) l; the boundary between rows is the tilted
 // plane z = tau_r l with tau_r = v_r / D.  Seen from the top, detector column
 // k cuts pixel (ix, iy) in a convex polygon P (the paper's triangles and
-// trapezoids of Sec. III-B).  Because the row planes depend on (x, y) only
-// through l, the volume of P x [za, za + c] below row plane r is
-//     H = integral over P of clamp(e + tau l', 0, c) dA,  e = tau lc - za,
-// a one-dimensional integral of the chord length w(l') of P against a clamped
-// linear height.  w is piecewise linear with kinks at the vertex depths of P,
-// so between consecutive vertex depths every piece is a prismatoid whose
-// volume is exact by the prismatoid rule (appendix, "Prismatoid"); the piece
-// cut by a row plane is the tetrahedron / wedge of Sec. III-C.  The weight of
-// detector element (k, r) is the difference of H between its two row planes
-// (the vol_res differencing of Sec. III-C).  Summing the pieces in depth order
-// from the far end, with moments taken about each breakpoint, keeps every term
-// non-negative, so nothing cancels near phi = k pi / 2 where the closed forms
-// of the paper divide by sin(phi) or by vanishing depth gaps.
+// trapezoids of Sec. III-B).  The row planes depend on (x, y) only through l,
+// so the volume of the column P x [z, inf) lying below plane r is
+//     K(z) = integral over P of (e + tau l')_+ dA,   e = tau lc - z,
+// a one-dimensional integral of the chord length w(l') of P against a
+// truncated linear height.  w is piecewise linear with kinks at the vertex
+// depths of P; between consecutive vertex depths each piece is a prismatoid
+// whose volume the prismatoid rule gives exactly (appendix, "Prismatoid"), and
+// the piece cut by the plane is the tetrahedron / wedge of Sec. III-C.  The
+// volume of voxel [za, zb] below the plane is K(za) - K(zb), and the weight of
+// detector element (k, r) is the difference of that between its two row
+// planes (the vol_res differencing of Sec. III-C).  Summing pieces from the
+// far end with moments about each breakpoint keeps every term non-negative,
+// so nothing cancels near phi = k pi / 2, where the paper's closed forms
+// divide by sin(phi) or by vanishing depth gaps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -50,35 +51,33 @@ struct DevGeom {
     const double *tau;      // nv + 1 row-plane slopes v_r / D
 };
 
-constexpr int MAXB = 8;  // breakpoints of a strip polygon (<= 6 in exact arithmetic)
+constexpr int MAXV = 6;  // vertices of a strip polygon (rectangle cut by two lines)
 
-// Strip record: pixel (ix, iy) cut by detector column k in one view.
-// tab[0] lists the breakpoints in ascending l', tab[1] in ascending -l'
-// (the mirror image used by row planes with tau < 0).  Each entry is
-// (depth, chord width, S0, S1) with S0 = integral of w beyond the depth and
-// S1 = first moment of w beyond the depth about the depth itself.
+// Strip record: pixel `pix` cut by detector column k in one view.
+// tab[i] = (depth l', chord width w, S0, S1) for the breakpoints in ascending
+// depth, S0 = integral of w beyond the depth, S1 = first moment of w beyond
+// the depth about the depth itself.  Area = tab[0][2].
 template <typename T>
 struct alignas(16) Rec {
-    double lc;          // depth of the column centre
-    double lmin, lmax;  // absolute depth range of the polygon
-    double ilmin, ilmax;  // their reciprocals
-    T area;             // polygon area
-    int n;              // number of breakpoints, 0 when the polygon is empty
-    int k;              // detector column
-    int pix;            // pixel index iy * nx + ix (or a kernel-local index)
-    T tab[2][MAXB][4];
+    double lc;  // depth of the pixel centre
+    int n;      // number of breakpoints, 0 when the polygon is empty
+    int k;      // detector column
+    int pix;    // pixel index iy * nx + ix
+    int pad;
+    T tab[MAXV][4];
 };
 
-__device__ __forceinline__ double2 view_trig(const DevGeom &G, int view) { return G.trig[view]; }
+__host__ __device__ inline double dmin_(double a, double b) { return a < b ? a : b; }
+__host__ __device__ inline double dmax_(double a, double b) { return a > b ? a : b; }
 
 // ---------------------------------------------------------------------------
 // strip polygon: pixel rectangle cut by the wedge u_k <= u <= u_{k+1}
 // ---------------------------------------------------------------------------
-// Builds the record in FP64 (the plane/face intersections and every sign
-// decision), then stores the tables in T.
-template <typename T>
-__host__ __device__ void build_record(const DevGeom &G, double cp, double sp, int ix, int iy, int k,
-                             Rec<T> &R)
+// FP64 throughout (the plane/face intersections and every sign decision);
+// the tables are stored in T.  `ws` is scratch for up to 8 vertices.
+template <typename T, typename RecT>
+__host__ __device__ inline void build_record(const DevGeom &G, double cp, double sp, int ix, int iy,
+                                             int k, RecT &R, double2 *ws)
 {
     const double xc = G.x0 + ((double)ix + 0.5) * G.a;
     const double yc = G.y0 + ((double)iy + 0.5) * G.b;
@@ -108,166 +107,179 @@ __host__ __device__ void build_record(const DevGeom &G, double cp, double sp, in
         g1[j] = ct[j] - mu1 * cd[j] + ep1;  // <= 0: u <= u_{k+1}
     }
 
-    // polygon vertices (cyclic): kept corners and crossings in edge order
-    double vd[MAXB], vt[MAXB];
+    // polygon vertices in cyclic order: kept corners and crossings in edge order
     int m = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int jn = (j + 1) & 3;
-        if (g0[j] >= 0.0 && g1[j] <= 0.0 && m < MAXB) {
-            vd[m] = cd[j];
-            vt[m] = ct[j];
+        if (g0[j] >= 0.0 && g1[j] <= 0.0) {
+            if (m < 8) ws[m] = make_double2(cd[j], ct[j]);
             ++m;
         }
         double s0 = -1.0, s1 = -1.0;
         if ((g0[j] > 0.0 && g0[jn] < 0.0) || (g0[j] < 0.0 && g0[jn] > 0.0)) s0 = g0[j] / (g0[j] - g0[jn]);
         if ((g1[j] > 0.0 && g1[jn] < 0.0) || (g1[j] < 0.0 && g1[jn] > 0.0)) s1 = g1[j] / (g1[j] - g1[jn]);
-        double sa = s0, sb = s1;
-        if (sa > sb) {
-            double tmp = sa;
-            sa = sb;
-            sb = tmp;
-        }
-        if (sa >= 0.0 && m < MAXB) {
-            vd[m] = cd[j] + sa * (cd[jn] - cd[j]);
-            vt[m] = ct[j] + sa * (ct[jn] - ct[j]);
+        const double sa = dmin_(s0, s1), sb = dmax_(s0, s1);
+        if (sa >= 0.0) {
+            if (m < 8) ws[m] = make_double2(cd[j] + sa * (cd[jn] - cd[j]), ct[j] + sa * (ct[jn] - ct[j]));
             ++m;
         }
-        if (sb >= 0.0 && m < MAXB) {
-            vd[m] = cd[j] + sb * (cd[jn] - cd[j]);
-            vt[m] = ct[j] + sb * (ct[jn] - ct[j]);
+        if (sb >= 0.0) {
+            if (m < 8) ws[m] = make_double2(cd[j] + sb * (cd[jn] - cd[j]), ct[j] + sb * (ct[jn] - ct[j]));
             ++m;
         }
+    }
+    if (m > 8) m = 8;
+    // drop vertices that repeat their predecessor (rounding residue of a cut
+    // through a corner); a convex cut of a rectangle by two lines keeps <= 6
+    {
+        const double tol = 1e-12 * (G.a + G.b);
+        int w = 0;
+        for (int i = 0; i < m; ++i) {
+            const double2 v = ws[i];
+            if (w > 0) {
+                const double2 p = ws[w - 1];
+                if (fabs(v.x - p.x) <= tol && fabs(v.y - p.y) <= tol) continue;
+            }
+            ws[w++] = v;
+        }
+        while (w > 1 && fabs(ws[w - 1].x - ws[0].x) <= tol && fabs(ws[w - 1].y - ws[0].y) <= tol) --w;
+        m = w > MAXV ? MAXV : w;
     }
 
     R.lc = lc;
     R.k = k;
     if (m < 3) {
         R.n = 0;
-        R.area = T(0);
-        R.lmin = lc;
-        R.lmax = lc;
-        R.ilmin = 1.0 / lc;
-        R.ilmax = R.ilmin;
         return;
     }
 
-    // breakpoints: vertex depths in ascending order (insertion sort, m <= 8)
-    double bd[MAXB];
+    // breakpoints: vertex depths in ascending order
+    double bd[MAXV];
 #pragma unroll
-    for (int i = 0; i < MAXB; ++i) bd[i] = (i < m) ? vd[i] : 1e300;
+    for (int i = 0; i < MAXV; ++i) bd[i] = (i < m) ? ws[i].x : 1e300;
 #pragma unroll
-    for (int i = 1; i < MAXB; ++i) {
+    for (int i = 1; i < MAXV; ++i) {
 #pragma unroll
         for (int j = i; j > 0; --j) {
             const double lo = bd[j - 1], hi = bd[j];
-            const bool sw = lo > hi;
-            bd[j - 1] = sw ? hi : lo;
-            bd[j] = sw ? lo : hi;
+            bd[j - 1] = dmin_(lo, hi);
+            bd[j] = dmax_(lo, hi);
         }
     }
-
-    // chord width at each breakpoint: extent in t' of the polygon's
-    // intersection with the line l' = depth; an edge of zero depth extent
-    // contributes both end points (the inner limit at an extreme depth).
-    double bw[MAXB];
+    // polygon edges (depth-ordered end points)
+    double ea[MAXV], eb[MAXV], ta[MAXV], tb[MAXV];
 #pragma unroll
-    for (int i = 0; i < MAXB; ++i) {
+    for (int e = 0; e < MAXV; ++e) {
+        const double2 p = ws[e < m ? e : 0];
+        const double2 q = ws[(e + 1 < m) ? e + 1 : 0];
+        const bool sw = p.x > q.x;
+        ea[e] = sw ? q.x : p.x;
+        eb[e] = sw ? p.x : q.x;
+        ta[e] = sw ? q.y : p.y;
+        tb[e] = sw ? p.y : q.y;
+    }
+    // chord width at each breakpoint: extent in t' of the polygon's section at
+    // that depth; an edge of zero depth extent contributes both end points
+    // (the inner limit at an extreme depth)
+    double bw[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
         double tmin = 1e300, tmax = -1e300;
         const double dq = bd[i];
-        for (int e = 0; e < m; ++e) {
-            const int en = (e + 1 == m) ? 0 : e + 1;
-            double da = vd[e], db = vd[en], ta = vt[e], tb = vt[en];
-            if (da > db) {
-                double t1 = da; da = db; db = t1;
-                t1 = ta; ta = tb; tb = t1;
-            }
-            if (dq < da || dq > db) continue;
-            if (db == da) {
-                tmin = fmin(tmin, fmin(ta, tb));
-                tmax = fmax(tmax, fmax(ta, tb));
-            } else {
-                const double tq = ta + (tb - ta) * ((dq - da) / (db - da));
-                tmin = fmin(tmin, tq);
-                tmax = fmax(tmax, tq);
+#pragma unroll
+        for (int e = 0; e < MAXV; ++e) {
+            if (e < m && dq >= ea[e] && dq <= eb[e]) {
+                if (eb[e] == ea[e]) {
+                    tmin = dmin_(tmin, dmin_(ta[e], tb[e]));
+                    tmax = dmax_(tmax, dmax_(ta[e], tb[e]));
+                } else {
+                    const double tq = ta[e] + (tb[e] - ta[e]) * ((dq - ea[e]) / (eb[e] - ea[e]));
+                    tmin = dmin_(tmin, tq);
+                    tmax = dmax_(tmax, tq);
+                }
             }
         }
         bw[i] = (i < m && tmax >= tmin) ? (tmax - tmin) : 0.0;
     }
-
-    // suffix moments (ascending table) and prefix moments (mirrored table);
-    // each slab between breakpoints is a prismatoid: integral of w is
-    // L (w_i + w_i+1) / 2, the moment about the near end L^2 (w_near/3 + w_far/6)
-    double S0[MAXB], S1[MAXB], P0[MAXB], P1[MAXB];
-    S0[m - 1] = 0.0;
-    S1[m - 1] = 0.0;
-    for (int i = m - 2; i >= 0; --i) {
-        const double L = bd[i + 1] - bd[i];
-        S0[i] = S0[i + 1] + 0.5 * L * (bw[i] + bw[i + 1]);
-        S1[i] = S1[i + 1] + L * S0[i + 1] + L * L * (bw[i] * (1.0 / 6.0) + bw[i + 1] * (1.0 / 3.0));
+    // suffix moments: each slab between breakpoints is a prismatoid; its
+    // integral of w is L (w_i + w_i+1) / 2 and its moment about the near end
+    // L^2 (w_i / 6 + w_i+1 / 3)
+    double S0[MAXV], S1[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) S0[i] = S1[i] = 0.0;
+#pragma unroll
+    for (int i = MAXV - 2; i >= 0; --i) {
+        if (i < m - 1) {
+            const double L = bd[i + 1] - bd[i];
+            S0[i] = S0[i + 1] + 0.5 * L * (bw[i] + bw[i + 1]);
+            S1[i] = S1[i + 1] + L * S0[i + 1] + L * L * (bw[i] * (1.0 / 6.0) + bw[i + 1] * (1.0 / 3.0));
+        }
     }
-    P0[0] = 0.0;
-    P1[0] = 0.0;
-    for (int i = 1; i < m; ++i) {
-        const double L = bd[i] - bd[i - 1];
-        P0[i] = P0[i - 1] + 0.5 * L * (bw[i - 1] + bw[i]);
-        P1[i] = P1[i - 1] + L * P0[i - 1] + L * L * (bw[i] * (1.0 / 6.0) + bw[i - 1] * (1.0 / 3.0));
-    }
-    const double area = S0[0];
-    R.n = (area > 0.0) ? m : 0;
-    R.area = T(area);
-    R.lmin = lc + bd[0];
-    R.lmax = lc + bd[m - 1];
-    R.ilmin = 1.0 / R.lmin;
-    R.ilmax = 1.0 / R.lmax;
-    for (int i = 0; i < m; ++i) {
-        R.tab[0][i][0] = T(bd[i]);
-        R.tab[0][i][1] = T(bw[i]);
-        R.tab[0][i][2] = T(S0[i]);
-        R.tab[0][i][3] = T(S1[i]);
-        const int j = m - 1 - i;
-        R.tab[1][j][0] = T(-bd[i]);
-        R.tab[1][j][1] = T(bw[i]);
-        R.tab[1][j][2] = T(P0[i]);
-        R.tab[1][j][3] = T(P1[i]);
+    R.n = S0[0] > 0.0 ? m : 0;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+        R.tab[i][0] = T(i < m ? bd[i] : bd[m - 1]);
+        R.tab[i][1] = T(bw[i]);
+        R.tab[i][2] = T(S0[i]);
+        R.tab[i][3] = T(S1[i]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// cumulative sub-volume below a row plane
+// cumulative volume above a face and below a row plane
 // ---------------------------------------------------------------------------
-// Psi(lambda) = integral over P of (l'' - lambda)_+ dA for lambda inside the
-// table's depth range (l'' = l' for table 0, -l' for table 1).
+__host__ __device__ inline float rcp_(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+__host__ __device__ inline double rcp_(double x) { return 1.0 / x; }
+
+// Psi(lam) = integral over P of (l' - lam)_+ dA for lam inside [d_0, d_n-1].
 template <typename T>
 __host__ __device__ inline T psi_inside(const T (*tab)[4], int n, T lam)
 {
-    int i = 0;
-    for (int j = 1; j < n - 1; ++j) i += (lam >= tab[j][0]) ? 1 : 0;
-    const T d0 = tab[i][0], w0 = tab[i][1];
-    const T d1 = tab[i + 1][0], w1 = tab[i + 1][1], s0 = tab[i + 1][2], s1 = tab[i + 1][3];
+    T d0 = tab[0][0], w0 = tab[0][1], d1 = tab[1][0], w1 = tab[1][1], s0 = tab[1][2],
+      s1 = tab[1][3];
+#pragma unroll
+    for (int j = 1; j < MAXV - 1; ++j) {
+        if (j < n - 1 && lam >= tab[j][0]) {
+            d0 = tab[j][0];
+            w0 = tab[j][1];
+            d1 = tab[j + 1][0];
+            w1 = tab[j + 1][1];
+            s0 = tab[j + 1][2];
+            s1 = tab[j + 1][3];
+        }
+    }
     const T L = d1 - d0;
     T h = d1 - lam;
     h = h < T(0) ? T(0) : (h > L ? L : h);
-    const T wl = w1 + (w0 - w1) * (L > T(0) ? h / L : T(0));
+    const T wl = w1 + (w0 - w1) * (L > T(0) ? h * rcp_(L) : T(0));
     return h * h * (wl * T(1.0 / 6.0) + w1 * T(1.0 / 3.0)) + s1 + h * s0;
 }
 
-// Volume of (polygon x [za, za + c]) below the plane z = tau l, given
-// e = tau lc - za (plane height above the voxel bottom at the column centre),
-// at = |tau|, inv_at = 1 / at (unused when at == 0) and sg = (tau < 0).
+// K = integral over P of (e + tau l')_+ dA: the volume of the column above a
+// face and below the plane z = tau l, with e = tau lc - z_face the plane's
+// height above the face at the column centre.  inv_tau = 1 / tau (any value
+// when tau == 0).
 template <typename T>
-__host__ __device__ inline T eval_H(const Rec<T> &R, int sg, T at, T inv_at, T e, T c)
+__host__ __device__ inline T eval_K(const T (*tab)[4], int n, T tau, T inv_tau, T e)
 {
-    const T (*tab)[4] = R.tab[sg];
-    const int n = R.n;
-    const T d0 = tab[0][0], dn = tab[n - 1][0];
-    const T A = R.area;
-    const T lo = e + at * d0, hi = e + at * dn;
-    if (hi <= T(0)) return T(0);
-    if (lo >= c) return c * A;
-    const T p0 = (lo >= T(0)) ? (lo * A + at * tab[0][3]) : at * psi_inside(tab, n, -e * inv_at);
-    const T p1 = (hi <= c) ? T(0) : at * psi_inside(tab, n, (c - e) * inv_at);
-    return p0 - p1;
+    const T d0 = tab[0][0], dn = tab[n - 1][0], A = tab[0][2], S1 = tab[0][3];
+    const T h0 = e + tau * d0, h1 = e + tau * dn;  // heights at the near and far ends
+    const T hmax = h0 > h1 ? h0 : h1, hmin = h0 > h1 ? h1 : h0;
+    if (hmax <= T(0)) return T(0);
+    if (hmin >= T(0)) return h0 * A + tau * S1;  // e A + tau * (first moment)
+    const T lam = -e * inv_tau;                  // depth where the plane meets the face
+    const T psi = psi_inside(tab, n, lam);
+    if (tau > T(0)) return tau * psi;
+    // tau < 0: integral of (lam - l')_+ = Psi - S1 + (lam - d0) A
+    return (-tau) * (psi - S1 + (lam - d0) * A);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,36 +339,34 @@ __host__ __device__ inline void strip_minor_range(const DevGeom &G, const StripA
     double lo = 1e300, hi = -1e300;
     if (A.major_x) {
         const double xa = G.x0 + (double)i * G.a, xb = xa + G.a;
-#pragma unroll
         for (int q = 0; q < 2; ++q) {
             const double us = q ? uhi : ulo;
             const double den = G.D * cp + us * sp;
             const double ya = (us * G.s + xa * (G.D * sp - us * cp)) / den;
             const double yb = (us * G.s + xb * (G.D * sp - us * cp)) / den;
-            lo = fmin(lo, fmin(ya, yb));
-            hi = fmax(hi, fmax(ya, yb));
+            lo = dmin_(lo, dmin_(ya, yb));
+            hi = dmax_(hi, dmax_(ya, yb));
         }
         const double pad = 1e-9 * G.b;
         double f0 = floor((lo - pad - G.y0) / G.b), f1 = floor((hi + pad - G.y0) / G.b);
         if (!(f0 == f0) || !(f1 == f1)) { f0 = 0; f1 = A.n_minor - 1; }
-        j0 = (int)fmin(fmax(f0, 0.0), (double)A.n_minor);
-        j1 = (int)fmax(fmin(f1, (double)(A.n_minor - 1)), -1.0);
+        j0 = (int)dmin_(dmax_(f0, 0.0), (double)A.n_minor);
+        j1 = (int)dmax_(dmin_(f1, (double)(A.n_minor - 1)), -1.0);
     } else {
         const double ya = G.y0 + (double)i * G.b, yb = ya + G.b;
-#pragma unroll
         for (int q = 0; q < 2; ++q) {
             const double us = q ? uhi : ulo;
             const double den = us * cp - G.D * sp;
             const double xa = (us * (G.s - ya * sp) - G.D * ya * cp) / den;
             const double xb = (us * (G.s - yb * sp) - G.D * yb * cp) / den;
-            lo = fmin(lo, fmin(xa, xb));
-            hi = fmax(hi, fmax(xa, xb));
+            lo = dmin_(lo, dmin_(xa, xb));
+            hi = dmax_(hi, dmax_(xa, xb));
         }
         const double pad = 1e-9 * G.a;
         double f0 = floor((lo - pad - G.x0) / G.a), f1 = floor((hi + pad - G.x0) / G.a);
         if (!(f0 == f0) || !(f1 == f1)) { f0 = 0; f1 = A.n_minor - 1; }
-        j0 = (int)fmin(fmax(f0, 0.0), (double)A.n_minor);
-        j1 = (int)fmax(fmin(f1, (double)(A.n_minor - 1)), -1.0);
+        j0 = (int)dmin_(dmax_(f0, 0.0), (double)A.n_minor);
+        j1 = (int)dmax_(dmin_(f1, (double)(A.n_minor - 1)), -1.0);
     }
 }
 
@@ -375,19 +385,29 @@ __host__ __device__ inline void corner_columns(const DevGeom &G, double cp, doub
         const double l = G.s - (x * cp + y * sp);
         const double t = y * cp - x * sp;
         const double u = G.D * t / l;
-        umin = fmin(umin, u);
-        umax = fmax(umax, u);
+        umin = dmin_(umin, u);
+        umax = dmax_(umax, u);
     }
     const double pad = 1e-9 * G.du;
     const double f0 = floor((umin - pad - G.u0) / G.du), f1 = floor((umax + pad - G.u0) / G.du);
-    k0 = (int)fmin(fmax(f0, 0.0), (double)G.nu);
-    k1 = (int)fmax(fmin(f1, (double)(G.nu - 1)), -1.0);
+    k0 = (int)dmin_(dmax_(f0, 0.0), (double)G.nu);
+    k1 = (int)dmax_(dmin_(f1, (double)(G.nu - 1)), -1.0);
 }
 
-__device__ __forceinline__ void pixel_columns(const DevGeom &G, double cp, double sp, int ix,
+__host__ __device__ inline void pixel_columns(const DevGeom &G, double cp, double sp, int ix,
                                               int iy, int &k0, int &k1)
 {
     corner_columns(G, cp, sp, ix, ix + 1, iy, iy + 1, k0, k1);
+}
+
+// Position of pixel (ix, iy) in the walk of a strip whose per-major table is
+// (j0[i], off[i], off[i+1]); -1 when the pixel is not in the strip.
+__host__ __device__ inline int strip_position(bool major_x, int ix, int iy, const int *j0,
+                                              const int *off)
+{
+    const int i = major_x ? ix : iy, j = major_x ? iy : ix;
+    const int a = j0[i], cnt = off[i + 1] - off[i];
+    return (j >= a && j < a + cnt) ? off[i] + (j - a) : -1;
 }
 
 // XCD-aware block order: consecutive logical blocks land on the same XCD so
@@ -399,8 +419,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nblocks)
     const int per = (nblocks + nx - 1) / nx;
     const int xcd = b % nx, slot = b / nx;
     const int full = nblocks % nx == 0 ? nx : nblocks % nx;  // XCDs holding `per` blocks
-    // XCDs [0, full) own `per` logical blocks, the rest own per - 1
-    int base = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1);
+    const int base = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1);
     return base + slot;
 }
 

@@ -69,7 +69,7 @@ __global__ void footprints_kernel(DevGeom G, int view, int32_t *boxes)
     const int ix = (int)(j % G.nx);
     const int iy = (int)((j / G.nx) % G.ny);
     const int iz = (int)(j / ((int64_t)G.nx * G.ny));
-    const double2 cs = view_trig(G, view);
+    const double2 cs = G.trig[view];
     int box[4];
     footprint_box(G, cs.x, cs.y, ix, iy, iz, box);
     for (int q = 0; q < 4; ++q) boxes[4 * j + q] = box[q];
@@ -91,7 +91,7 @@ template <typename F>
 __device__ void voxel_view_weights(const DevGeom &G, int view, int ix, int iy, int iz,
                                    double tau_keep, bool want32, F fn)
 {
-    const double2 cs = view_trig(G, view);
+    const double2 cs = G.trig[view];
     const double cp = cs.x, sp = cs.y;
     int k0, k1;
     pixel_columns(G, cp, sp, ix, iy, k0, k1);
@@ -115,52 +115,61 @@ __device__ void voxel_view_weights(const DevGeom &G, int view, int ix, int iy, i
         return;
     }
     const double za = G.z0 + (double)iz * G.c, zb = za + G.c;
+    double2 ws[8];
     for (int k = k0; k <= k1; ++k) {
         Rec<double> R;
-        build_record<double>(G, cp, sp, ix, iy, k, R);
-        if (R.n == 0) continue;
+        build_record<double>(G, cp, sp, ix, iy, k, R, ws);
+        const int n = R.n;
+        if (n == 0) continue;
         Rec<float> Rf;
-        if (want32) build_record<float>(G, cp, sp, ix, iy, k, Rf);
+        if (want32) build_record<float>(G, cp, sp, ix, iy, k, Rf, ws);
+        const double lmin = R.lc + R.tab[0][0], lmax = R.lc + R.tab[n - 1][0];
         // planes cutting the voxel inside the strip: [pf, pl]; estimated from
         // the slope where the plane's highest (lowest) point meets za (zb),
         // then settled with exact comparisons
-        const double tst = za >= 0.0 ? za * R.ilmax : za * R.ilmin;
+        const double tst = za / (za >= 0.0 ? lmax : lmin);
         int pf = (int)fmin(fmax(floor((tst * G.D - G.v0) / G.dv) + 1.0, 0.0), (double)(G.nv + 1));
         while (pf > 0) {
             const double t = G.tau[pf - 1];
-            if (t * (t >= 0.0 ? R.lmax : R.lmin) > za) --pf; else break;
+            if (t * (t >= 0.0 ? lmax : lmin) > za) --pf; else break;
         }
         while (pf <= G.nv) {
             const double t = G.tau[pf];
-            if (!(t * (t >= 0.0 ? R.lmax : R.lmin) > za)) ++pf; else break;
+            if (!(t * (t >= 0.0 ? lmax : lmin) > za)) ++pf; else break;
         }
-        const double tss = zb >= 0.0 ? zb * R.ilmin : zb * R.ilmax;
+        const double tss = zb / (zb >= 0.0 ? lmin : lmax);
         int pl = (int)fmin(fmax(ceil((tss * G.D - G.v0) / G.dv) - 1.0, -1.0), (double)G.nv);
         while (pl < G.nv) {
             const double t = G.tau[pl + 1];
-            if (t * (t >= 0.0 ? R.lmin : R.lmax) < zb) ++pl; else break;
+            if (t * (t >= 0.0 ? lmin : lmax) < zb) ++pl; else break;
         }
         while (pl >= 0) {
             const double t = G.tau[pl];
-            if (!(t * (t >= 0.0 ? R.lmin : R.lmax) < zb)) --pl; else break;
+            if (!(t * (t >= 0.0 ? lmin : lmax) < zb)) --pl; else break;
         }
         const int r0 = max(pf - 1, 0), r1 = min(pl, G.nv - 1);
+        const double cA = G.c * R.tab[0][2];
+        const float cA32 = want32 ? (float)G.c * Rf.tab[0][2] : 0.f;
         double Hlo = 0.0;
         float Hlo32 = 0.f;
         for (int r = r0; r <= r1 + 1 && r <= G.nv; ++r) {
-            // H at plane r
+            // volume of the voxel below plane r: K(za) - K(zb)
             double H;
             float H32 = 0.f;
-            if (r < pf) { H = 0.0; }
-            else if (r > pl) { H = G.c * (double)R.area; if (want32) H32 = (float)G.c * Rf.area; }
-            else {
+            if (r < pf) {
+                H = 0.0;
+            } else if (r > pl) {
+                H = cA;
+                H32 = cA32;
+            } else {
                 const double t = G.tau[r];
-                const double at = fabs(t);
-                H = eval_H<double>(R, t < 0.0, at, at > 0.0 ? 1.0 / at : 0.0, t * R.lc - za, G.c);
+                const double it = t != 0.0 ? 1.0 / t : 0.0;
+                const double ea = t * R.lc - za;
+                H = eval_K<double>(R.tab, n, t, it, ea) - eval_K<double>(R.tab, n, t, it, ea - G.c);
                 if (want32) {
-                    const float af = (float)at;
-                    H32 = eval_H<float>(Rf, t < 0.0, af, af > 0.f ? 1.f / af : 0.f,
-                                        (float)(t * R.lc - za), (float)G.c);
+                    const float tf = (float)t, itf = tf != 0.f ? 1.f / tf : 0.f;
+                    H32 = eval_K<float>(Rf.tab, Rf.n, tf, itf, (float)ea) -
+                          eval_K<float>(Rf.tab, Rf.n, tf, itf, (float)(ea - G.c));
                 }
             }
             if (r > r0) {

@@ -13,22 +13,76 @@ namespace smk {
 struct LaunchCfg {
     int fwd_threads;   // 64 * ceil(nv / 64)
     int back_threads;  // 64 * ceil(nz / 64)
-    int back_tile_x[4], back_tile_y[4];  // adjoint pixel tile per batch width 1, 2, 4, 8
-    int back_pcols[4];                   // detector columns a tile can meet (max over views)
-    int back_rmax;                       // strip records staged per round
-    int lds_budget;                      // dynamic LDS bytes a workgroup may use
+    int back_pcols[4]; // detector columns an adjoint tile can meet (max over views)
+    int lds_budget;    // dynamic LDS bytes a workgroup may use
 };
 
-// x[B][nz][ny][nx] -> xt[ny][nx][B][nz] and back
-hipError_t launch_to_columns(const void *x, void *xt, int elem, int B, int nz, int ny, int nx,
-                             hipStream_t st);
+// Workspace of one call: strip records of a chunk of views, followed by the
+// per-call volume buffer (prefix sums for the forward, sums for the adjoint).
+struct RecLayout {
+    int cap;           // records per strip
+    int n_major_max;   // max(nx, ny)
+    int views;         // views per chunk
+    int pad;
+    int64_t recs_off, sj0_off, soff_off, pixk_off, data_off;  // byte offsets
+};
+
+struct RecPtrs {
+    void *recs;
+    int *sj0;
+    int *soff;
+    int2 *pixk;
+    char *data;
+};
+
+inline int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+inline RecLayout make_layout(int cap, int n_major_max, int views, int nu, int nx, int ny,
+                             size_t rec_size)
+{
+    RecLayout L;
+    L.cap = cap;
+    L.n_major_max = n_major_max;
+    L.views = views;
+    L.pad = 0;
+    const int64_t strips = (int64_t)views * nu;
+    L.recs_off = 0;
+    L.sj0_off = align256(L.recs_off + strips * cap * (int64_t)rec_size);
+    L.soff_off = align256(L.sj0_off + strips * n_major_max * (int64_t)sizeof(int));
+    L.pixk_off = align256(L.soff_off + strips * (n_major_max + 1) * (int64_t)sizeof(int));
+    L.data_off = align256(L.pixk_off + (int64_t)views * nx * ny * (int64_t)sizeof(int2));
+    return L;
+}
+
+inline RecPtrs rec_ptrs(const RecLayout &L, void *ws, size_t)
+{
+    char *b = (char *)ws;
+    RecPtrs P;
+    P.recs = b + L.recs_off;
+    P.sj0 = (int *)(b + L.sj0_off);
+    P.soff = (int *)(b + L.soff_off);
+    P.pixk = (int2 *)(b + L.pixk_off);
+    P.data = b + L.data_off;
+    return P;
+}
+
+// strip records for views [v0, v0 + nvc)
+hipError_t launch_records(const DevGeom &G, const RecLayout &RL, bool fp64, int v0, int nvc,
+                          void *ws, hipStream_t st);
+hipError_t launch_strip_count(const DevGeom &G, int *max_count, hipStream_t st);
+
+// x[B][nz][ny][nx] -> FP64 prefix sums along z, P[ny*nx][B][nz + 1]
+hipError_t launch_prefix_columns(const void *x, double *P, bool fp64, int B, int nz, int ny, int nx,
+                                 hipStream_t st);
+// xt[ny*nx][B][nz] -> x[B][nz][ny][nx]
 hipError_t launch_from_columns(const void *xt, void *x, int elem, int B, int nz, int ny, int nx,
                                hipStream_t st);
 
-hipError_t launch_fwd3d(const DevGeom &G, const LaunchCfg &L, bool fp64, const void *xt, void *y,
-                        int B, hipStream_t st);
-hipError_t launch_back3d(const DevGeom &G, const LaunchCfg &L, bool fp64, const void *y, void *xt,
-                         int B, hipStream_t st);
+hipError_t launch_fwd3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,
+                        int v0, int nvc, void *ws, const double *P, void *y, int B, hipStream_t st);
+hipError_t launch_back3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,
+                         int v0, int nvc, void *ws, const void *y, void *xt, int B, bool first,
+                         hipStream_t st);
 hipError_t launch_fwd2d(const DevGeom &G, bool fp64, const void *x, void *y, int B,
                         hipStream_t st);
 hipError_t launch_back2d(const DevGeom &G, bool fp64, const void *y, void *x, int B,

@@ -1,30 +1,48 @@
 // sm_transpose.hip -- layout changes between the caller's volume layout
-// x[B][nz][ny][nx] and the z-contiguous working layout xt[ny][nx][B][nz]
-// that the cone-beam kernels read and write (one voxel column of one batch
-// element is nz consecutive values).  Tiled 32 x 32 through LDS so both the
-// reads and the writes are coalesced.
+// x[B][nz][ny][nx] and the column layouts the cone-beam kernels use:
+//   forward input : FP64 prefix sums along z, P[ny*nx][B][nz + 1] with
+//                   P[.][.][0] = 0 and P[.][.][i+1] = x_0 + ... + x_i, so any
+//                   run of voxels of a column sums with one subtraction;
+//   adjoint output: xt[ny*nx][B][nz] (z contiguous), transposed back here.
+// Both go through LDS so global reads and writes stay coalesced.
 #include "sm_internal.h"
 
 namespace smk {
 
-// For each slab s = (b, iy): in[iz][ix] -> out[ix][iz].
+// One workgroup per (PW = 2^pwl consecutive pixels of one row, batch element).
 template <typename T>
-__global__ void __launch_bounds__(256) to_columns_kernel(const T *__restrict__ x, T *__restrict__ xt,
-                                                          int B, int nz, int ny, int nx)
+__global__ void __launch_bounds__(256) prefix_kernel(const T *__restrict__ x, double *__restrict__ P,
+                                                      int B, int nz, int ny, int nx, int pwl)
 {
-    __shared__ T tile[32][33];
-    const int s = blockIdx.z;
-    const int b = s / ny, iy = s - b * ny;
-    const int ix0 = blockIdx.x * 32, iz0 = blockIdx.y * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-    for (int j = ty; j < 32; j += 8) {
-        const int iz = iz0 + j, ix = ix0 + tx;
-        if (iz < nz && ix < nx) tile[j][tx] = x[(((size_t)b * nz + iz) * ny + iy) * nx + ix];
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *col = reinterpret_cast<double *>(smem);  // [PW][nz + 1]
+    const int tid = threadIdx.x;
+    const int PW = 1 << pwl;
+    const int nxb = (nx + PW - 1) / PW;
+    const int bi = blockIdx.x;
+    const int b = bi / (ny * nxb);
+    const int rem = bi - b * ny * nxb;
+    const int iy = rem / nxb, ix0 = (rem - iy * nxb) * PW;
+    const int w = min(PW, nx - ix0);
+    const int cs = nz + 1;
+    // load: PW consecutive x values per z slice
+    for (int q = tid; q < PW * nz; q += blockDim.x) {
+        const int iz = q >> pwl, i = q & (PW - 1);
+        if (i < w) col[i * cs + iz + 1] = (double)x[(((size_t)b * nz + iz) * ny + iy) * nx + ix0 + i];
     }
     __syncthreads();
-    for (int j = ty; j < 32; j += 8) {
-        const int ix = ix0 + j, iz = iz0 + tx;
-        if (iz < nz && ix < nx) xt[(((size_t)iy * nx + ix) * B + b) * nz + iz] = tile[tx][j];
+    if (tid < w) {  // sequential scan per column (fixed order)
+        double run = 0.0;
+        col[tid * cs] = 0.0;
+        for (int iz = 1; iz <= nz; ++iz) {
+            run += col[tid * cs + iz];
+            col[tid * cs + iz] = run;
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < w; ++i) {
+        double *dst = P + (((size_t)iy * nx + ix0 + i) * B + b) * cs;
+        for (int iz = tid; iz < cs; iz += blockDim.x) dst[iz] = col[i * cs + iz];
     }
 }
 
@@ -48,16 +66,21 @@ __global__ void __launch_bounds__(256) from_columns_kernel(const T *__restrict__
     }
 }
 
-hipError_t launch_to_columns(const void *x, void *xt, int elem, int B, int nz, int ny, int nx,
-                             hipStream_t st)
+hipError_t launch_prefix_columns(const void *x, double *P, bool fp64, int B, int nz, int ny, int nx,
+                                 hipStream_t st)
 {
-    dim3 grid((nx + 31) / 32, (nz + 31) / 32, B * ny);
-    if (elem == 8)
-        hipLaunchKernelGGL(to_columns_kernel<double>, grid, dim3(256), 0, st, (const double *)x,
-                           (double *)xt, B, nz, ny, nx);
+    int pwl = 4;  // 16 pixels per workgroup while the columns fit in 48 KiB of LDS
+    while (pwl > 0 && sizeof(double) * ((size_t)1 << pwl) * (size_t)(nz + 1) > 49152) --pwl;
+    const int PW = 1 << pwl;
+    const int nxb = (nx + PW - 1) / PW;
+    const dim3 grid((unsigned)B * ny * nxb);
+    const size_t lds = sizeof(double) * PW * (size_t)(nz + 1);
+    if (fp64)
+        hipLaunchKernelGGL(prefix_kernel<double>, grid, dim3(256), lds, st, (const double *)x, P, B,
+                           nz, ny, nx, pwl);
     else
-        hipLaunchKernelGGL(to_columns_kernel<float>, grid, dim3(256), 0, st, (const float *)x,
-                           (float *)xt, B, nz, ny, nx);
+        hipLaunchKernelGGL(prefix_kernel<float>, grid, dim3(256), lds, st, (const float *)x, P, B, nz,
+                           ny, nx, pwl);
     return hipGetLastError();
 }
 

@@ -48,9 +48,9 @@ class SystemMatrix:
         with torch.cuda.device(dev):
             _lib.check(L.sm_plan_create(C.byref(gs), prec, C.byref(plan)), "sm_plan_create")
         self._plan = plan
-        nv, nr, ws = C.c_int64(), C.c_int64(), C.c_int64()
-        _lib.check(L.sm_plan_sizes(plan, C.byref(nv), C.byref(nr), C.byref(ws)), "sm_plan_sizes")
-        self.n_vox, self.n_rays, self.ws_per_batch = nv.value, nr.value, ws.value
+        nv, nr = C.c_int64(), C.c_int64()
+        _lib.check(L.sm_plan_sizes(plan, C.byref(nv), C.byref(nr)), "sm_plan_sizes")
+        self.n_vox, self.n_rays = nv.value, nr.value
         self.vol_shape = (geometry.nz, geometry.ny, geometry.nx)
         self.sino_shape = (geometry.n_p, geometry.det_nz, geometry.det_ny)
 
@@ -81,8 +81,13 @@ class SystemMatrix:
             return t.shape[0]
         raise ValueError("%s has shape %s, expected %s or (B, *%s)" % (name, tuple(t.shape), shape, shape))
 
-    def workspace(self, batch: int) -> torch.Tensor:
-        return torch.empty(max(self.ws_per_batch * batch, 1), dtype=torch.uint8, device=self.device)
+    def workspace_bytes(self, batch: int = 1) -> int:
+        n = C.c_int64()
+        _lib.check(_lib.lib().sm_workspace_size(self._plan, int(batch), C.byref(n)), "sm_workspace_size")
+        return n.value
+
+    def workspace(self, batch: int = 1) -> torch.Tensor:
+        return torch.empty(max(self.workspace_bytes(batch), 1), dtype=torch.uint8, device=self.device)
 
     # -------------------------------------------------------------- operators
     def forward(self, x: torch.Tensor, out: torch.Tensor | None = None,
