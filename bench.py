@@ -8,9 +8,24 @@ whole volume/sinogram, inputs resident in HBM.  The metric counts exact
 nonzero voxel-detector pairs (W_ij > 1e-12 voxel volume) per second:
 value = 2 nnz / (t_forward + t_adjoint).
 
-Prints one JSON line (see the contract in the design doc).
+Prints one JSON line.  Besides the throughput it carries
+  roofline     -- the dominant kernel (largest summed launch time, timed with
+                  HIP events on the launch stream through sm_timing_*):
+                  algorithmic FP operations per launch / mean launch time,
+                  against the vector-ALU peak; traffic = HBM bytes per launch
+                  from the committed counter summary, null when the kernel
+                  sources changed since it was taken;
+  cpu_baseline -- the FP64 clipping oracle on a bounded sample.
+
+Extra modes (no GPU) turn rocprofv3 CSV output into the text summaries kept
+under profiles/:
+  --digest-stats KERNEL_STATS_CSV --out FILE --command "..."
+  --digest-counters FETCH_CSV WRITE_CSV --kernel NAME --copy-mib N --out FILE --command "..."
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -20,9 +35,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-# VALU issue rate with packed FP32 disabled: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
-VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# Vector ALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop per FMA x 2.4 GHz =
+# 78.6 TFLOP/s.  That is the FP64 rate and the FP32 rate without packed-FP32
+# instructions, which this library's build disables.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Algorithmic FP operations per nonzero pair: one evaluation of the
+# cumulative column volume K on its piecewise branch (21 flop) plus the
+# pair's multiply-add (2 flop).
+FLOP_PER_PAIR = 23
+KERNEL_SYMBOL = {"forward": "fwd3d_kernel", "adjoint": "back3d_kernel",
+                 "records": "rec_kernel", "prefix": "prefix_kernel",
+                 "transpose": "from_columns_kernel"}
 
 
 def parse():
@@ -33,43 +57,169 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--config", default="c3", choices=["c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=16)
+    ap.add_argument("--cpu-views", type=int, default=0,
+                    help="views in the oracle sample (default: one per oracle thread)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB "
+                         "(reference for HBM counters)")
+    ap.add_argument("--digest-stats", metavar="CSV")
+    ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--kernel", default="back3d_kernel")
+    ap.add_argument("--out")
+    ap.add_argument("--command", default="")
     return ap.parse_args()
 
 
+# ----------------------------------------------------------------- profiles
+def sources_digest():
+    """sha256 over the HIP sources and build flags of the library."""
+    h = hashlib.sha256()
+    pkg = os.path.join(ROOT, "paper_2511_12235_amd")
+    files = sorted(glob.glob(os.path.join(pkg, "csrc", "*"))) + [os.path.join(pkg, "build.py")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counters_file(config, precision, kernel):
+    return os.path.join(ROOT, "profiles", "%s_%s_%s_hbm_counters.txt"
+                        % (kernel, "cone256" if config == "c3" else "cone128", precision))
+
+
+def read_summary(path):
+    vals = {}
+    if not os.path.exists(path):
+        return vals
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    return vals
+
+
+def traffic_per_launch(config, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the library sources changed since."""
+    s = read_summary(counters_file(config, precision, kernel))
+    if not s or s.get("sources_sha256") != sources_digest():
+        return None
+    try:
+        return float(s["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def digest_stats(args):
+    rows = _rows(args.digest_stats)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 --kernel-trace --stats summary", "command: %s" % args.command, "",
+             "%-60s %7s %12s %12s %7s" % ("kernel", "calls", "avg_ms", "total_ms", "pct")]
+    for r in rows:
+        name = r["Name"]
+        short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        lines.append("%-60s %7s %12.4f %12.3f %7.2f" % (short[:60], r["Calls"], float(r["AverageNs"]) / 1e6,
+                                                       float(r["TotalDurationNs"]) / 1e6,
+                                                       float(r["Percentage"])))
+    _write(args.out, lines)
+
+
+def _per_dispatch(rows, counter, match):
+    vals = [float(r["Counter_Value"]) for r in rows
+            if r["Counter_Name"] == counter and match(r["Kernel_Name"])]
+    return vals
+
+
+def digest_counters(args):
+    fetch_rows, write_rows = _rows(args.digest_counters[0]), _rows(args.digest_counters[1])
+    is_k = lambda n: args.kernel in n
+    is_copy = lambda n: "copyBuffer" in n or ("copy" in n.lower() and args.kernel not in n)
+    fk = _per_dispatch(fetch_rows, "FETCH_SIZE", is_k)
+    wk = _per_dispatch(write_rows, "WRITE_SIZE", is_k)
+    fc = max(_per_dispatch(fetch_rows, "FETCH_SIZE", is_copy) or [0.0])
+    wc = max(_per_dispatch(write_rows, "WRITE_SIZE", is_copy) or [0.0])
+    if not fk or not wk or fc <= 0 or wc <= 0:
+        sys.exit("digest: kernel or copy dispatches missing from the counter files")
+    copy_kib = args.copy_mib * 1024.0
+    ff, wf = copy_kib / fc, copy_kib / wc
+    fetch = sum(fk) / len(fk)
+    write = sum(wk) / len(wk)
+    hbm = (fetch * ff + write * wf) * 1024.0
+    lines = ["# HBM traffic of %s from two rocprofv3 --pmc passes" % args.kernel,
+             "command: %s" % args.command,
+             "kernel: %s" % args.kernel,
+             "dispatches: %d" % len(fk),
+             "fetch_kib_per_dispatch: %.1f" % fetch,
+             "write_kib_per_dispatch: %.1f" % write,
+             "copy_mib: %d" % args.copy_mib,
+             "copy_fetch_kib: %.1f" % fc,
+             "copy_write_kib: %.1f" % wc,
+             "fetch_scale: %.5f" % ff,
+             "write_scale: %.5f" % wf,
+             "hbm_bytes_per_dispatch: %.0f" % hbm,
+             "sources_sha256: %s" % sources_digest()]
+    _write(args.out, lines)
+
+
+def _write(path, lines):
+    text = "\n".join(lines) + "\n"
+    if path:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as fh:
+            fh.write(text)
+    print(text, end="")
+
+
+# ------------------------------------------------------------- CPU baseline
 def cpu_baseline(g, n_views):
     """The FP64 oracle timed on a bounded sample of the same scanner: the
-    central 16-slice slab (nx x ny x 16 voxels), n_views views spread over
-    the scan, forward only (the adjoint visits the same pairs)."""
+    central 16-slice slab (nx x ny x 16 voxels) seen from n_views views spread
+    over the scan (one per oracle thread by default), forward W x only (the
+    adjoint visits the same pairs).  Pairs are counted by the oracle outside
+    the timed call."""
     import numpy as np
     from oracle import oracle as O
     from paper_2511_12235_amd import workloads as wl
-    slab = wl.make_geometry(3, (g.nx, g.ny, 16), (g.a, g.b, g.c), g.n_p, g.s, g.d,
-                            (g.det_ny, g.det_nz), (g.dy, g.dz), phi=g.phi)
-    x = wl.ellipse_phantom(slab, 10, seed=2)
-    views = np.linspace(0, g.n_p - 1, n_views).round().astype(np.int32)
-    counts = np.zeros(1, dtype=np.int64)
-    nnz = 0
-    for v in views:
-        rows, cols, vals = O.triplets(slab, views=(int(v), int(v) + 1))
-        nnz += len(vals)
+    threads = O.num_threads()
+    n_views = n_views if n_views > 0 else threads
+    views = np.linspace(0, g.n_p - 1, n_views).round().astype(np.int64)
+    sample = wl.make_geometry(3, (g.nx, g.ny, 16), (g.a, g.b, g.c), n_views, g.s, g.d,
+                              (g.det_ny, g.det_nz), (g.dy, g.dz), phi=np.asarray(g.phi)[views])
+    x = wl.ellipse_phantom(sample, 10, seed=2)
     t0 = time.perf_counter()
-    O.forward(slab, x, views=views)
+    O.forward(sample, x)
     dt = time.perf_counter() - t0
-    return {"value": nnz / dt, "unit": "pairs/s", "cores": O.num_threads(), "kind": "oracle",
+    nnz = O.count(sample)
+    return {"value": nnz / dt, "unit": "pairs/s", "cores": min(threads, n_views), "kind": "oracle",
             "sample": "FP64 clipping oracle, forward W x on the central 16-slice slab "
-                      "(%dx%dx16 voxels) of the 256^3 scanner, %d of %d views, %d pairs in %.1f s"
-                      % (g.nx, g.ny, n_views, g.n_p, nnz, dt)}
+                      "(%dx%dx16 voxels) of the %dx%dx%d scan, %d of its %d views, %d pairs in %.1f s"
+                      % (g.nx, g.ny, g.nx, g.ny, g.nz, n_views, g.n_p, nnz, dt)}
 
 
+# -------------------------------------------------------------------- bench
 def main():
     args = parse()
+    if args.digest_stats:
+        return digest_stats(args)
+    if args.digest_counters:
+        return digest_counters(args)
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); "
+        print("bench.py runs on one GPU only (this library has no multi-GPU path); "
               "got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    import ctypes as C
+
     import numpy as np
     import torch
+
+    from paper_2511_12235_amd import _lib
     from paper_2511_12235_amd import workloads as wl
     from paper_2511_12235_amd.projector import SystemMatrix
 
@@ -83,14 +233,20 @@ def main():
     xb = torch.empty(A.vol_shape, dtype=dt, device=dev)
 
     # exact number of nonzero pairs (FP64 pattern), counted on the GPU
-    import ctypes as C
-    from paper_2511_12235_amd import _lib
     nnz = C.c_int64(0)
     t0 = time.perf_counter()
     _lib.check(_lib.lib().sm_weights_csr(A._plan, _lib.SM_FP32, C.byref(nnz), None, None, None),
                "sm_weights_csr(count)")
     count_s = time.perf_counter() - t0
     nnz = nnz.value
+
+    if args.copy_mib > 0:  # plain copy of known size: reference for the HBM counters
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     stream = torch.cuda.current_stream(dev)
     for _ in range(args.warmup):
@@ -99,6 +255,7 @@ def main():
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    A.timing(True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     for e0, e1, e2 in ev:
@@ -109,11 +266,26 @@ def main():
         e2.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    kt = A.read_timing()
+    A.timing(False)
     t_f = np.array([a.elapsed_time(b) for a, b, _ in ev]) / 1e3
     t_b = np.array([b.elapsed_time(c) for _, b, c in ev]) / 1e3
     step = t_f + t_b
     value = 2.0 * nnz / float(np.mean(step))
     eff_bw = value * 8.0 / 1e9  # GB/s a stored FP32+int32 CSR matrix would stream
+
+    # dominant kernel: largest summed launch time in the timed region
+    dom = max(("forward", "adjoint", "records", "prefix", "transpose"), key=lambda k: kt[k][1])
+    launches, ms = kt[dom]
+    ms_launch = ms / max(launches, 1)
+    pairs_per_launch = nnz * args.steps / max(launches, 1) if dom in ("forward", "adjoint") else 0.0
+    achieved = FLOP_PER_PAIR * pairs_per_launch / (ms_launch / 1e3) / 1e12 if ms_launch > 0 else 0.0
+    traffic = traffic_per_launch(args.config, args.precision, KERNEL_SYMBOL[dom])
+    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic,
+                "kernel": KERNEL_SYMBOL[dom], "ms_per_launch": ms_launch,
+                "pairs_per_launch": pairs_per_launch, "flop_per_pair": FLOP_PER_PAIR}
+
     res = {
         "metric": "Wx+W^Ty voxel-detector pairs/s at 256^3 (% HBM roofline); p50/p99 solve latency",
         "value": value,
@@ -132,11 +304,13 @@ def main():
                    "nnz_pairs": nnz, "ms_forward": float(np.mean(t_f)) * 1e3,
                    "ms_adjoint": float(np.mean(t_b)) * 1e3, "nnz_count_s": count_s,
                    "wall_s": wall,
+                   "kernel_ms": {k: round(v[1] / args.steps, 3) for k, v in kt.items()},
                    "pct_hbm_roofline_effective": 100.0 * eff_bw / HBM_PEAK_GBS},
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(g, args.cpu_views)
-    print(json.dumps(res))
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -144,6 +144,39 @@ sm_status sm_weights_csr(const sm_plan *plan, sm_precision values, int64_t *nnz_
  * nx*ny*nz*4 int32.  Synchronises the current device. */
 sm_status sm_footprints(const sm_plan *plan, int32_t view, int32_t *boxes_host);
 
+/* Per-kernel timing, for measurement only (not part of the method).  While
+ * timing is enabled on a plan, sm_forward and sm_back record a pair of HIP
+ * events on their stream around every dispatch of the kernels below and add
+ * nothing else (no synchronisation).  One dispatch covers up to 8 batch
+ * elements; the 2D kernels count as SM_KERNEL_FORWARD / SM_KERNEL_ADJOINT. */
+typedef enum {
+    SM_KERNEL_RECORDS = 0,   /* strip polygons and chord tables (Sec. III-B) */
+    SM_KERNEL_FORWARD = 1,   /* y = W x accumulation (Sec. III-C) */
+    SM_KERNEL_ADJOINT = 2,   /* x = W^T y accumulation */
+    SM_KERNEL_PREFIX = 3,    /* column prefix sums of the forward input */
+    SM_KERNEL_TRANSPOSE = 4, /* adjoint output to the caller's layout */
+    SM_KERNEL_COUNT = 5
+} sm_kernel;
+
+typedef struct {
+    int64_t launches; /* dispatches timed since the last read */
+    double ms;        /* their summed event-to-event durations, milliseconds */
+} sm_kernel_time;
+
+/* Enable (enable != 0) or disable per-kernel timing on a plan.  Enabling
+ * creates a pool of 8192 events on the plan's device and clears previous
+ * records; disabling releases it.  While enabled, calls on this plan must not
+ * overlap in time from several host threads.  Must not be toggled while
+ * timed work is still in flight on some stream. */
+sm_status sm_timing_enable(sm_plan *plan, int32_t enable);
+
+/* Wait for the recorded events (host blocks until they have completed),
+ * write SM_KERNEL_COUNT entries to times_host indexed by sm_kernel, and
+ * clear the records.  Returns SM_EINVAL when timing is not enabled and
+ * SM_ERANGE (times still written) when more dispatches were made than the
+ * pool could time; the untimed ones are not counted. */
+sm_status sm_timing_read(sm_plan *plan, sm_kernel_time *times_host);
+
 /* Static text for a status code. */
 const char *sm_status_str(sm_status status);
 

@@ -171,6 +171,19 @@ def triplets(g, views=None, tau=None):
     return rows[order], cols[order], vals[order]
 
 
+def count(g, views=None, tau=None) -> int:
+    """Number of kept entries (W > tau) of the views [v0, v1) (all by default)."""
+    L = lib()
+    b = _Bound(g)
+    tau = default_tau(g) if tau is None else float(tau)
+    v0, v1 = (0, g.n_p) if views is None else (int(views[0]), int(views[1]))
+    counts = np.zeros(max(v1 - v0, 1), dtype=np.int64)
+    tot = L.orc_count(b.ref, v0, v1, tau, _ptr(counts, C.c_int64))
+    if tot < 0:
+        raise ValueError("invalid geometry: source inside or behind the grid")
+    return int(tot)
+
+
 def matrix(g, tau=None):
     """The full system matrix as a scipy CSR matrix (small problems)."""
     import scipy.sparse as sp

@@ -18,7 +18,16 @@ SM_FP32, SM_FP64 = 0, 1
 
 EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_workspace_size",
             "sm_forward", "sm_back",
-            "sm_weights_csr", "sm_footprints", "sm_status_str", "sm_last_error")
+            "sm_weights_csr", "sm_footprints", "sm_timing_enable", "sm_timing_read",
+            "sm_status_str", "sm_last_error")
+
+# sm_kernel ids (timing)
+KERNELS = ("records", "forward", "adjoint", "prefix", "transpose")
+
+
+class SmKernelTime(C.Structure):
+    """Mirror of ``sm_kernel_time`` in include/sm.h."""
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double)]
 
 
 class SmGeometry(C.Structure):
@@ -73,6 +82,10 @@ def lib():
         L.sm_weights_csr.argtypes = [vp, C.c_int, i64p, i64p, i32p, vp]
         L.sm_footprints.restype = C.c_int
         L.sm_footprints.argtypes = [vp, C.c_int32, i32p]
+        L.sm_timing_enable.restype = C.c_int
+        L.sm_timing_enable.argtypes = [vp, C.c_int32]
+        L.sm_timing_read.restype = C.c_int
+        L.sm_timing_read.argtypes = [vp, C.POINTER(SmKernelTime)]
         L.sm_status_str.restype = C.c_char_p
         L.sm_status_str.argtypes = [C.c_int]
         L.sm_last_error.restype = C.c_char_p

@@ -5,8 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
-
 #include <string>
 #include <vector>
 
@@ -15,6 +15,16 @@
 
 using smk::DevGeom;
 using smk::LaunchCfg;
+
+// Event-pair timing of individual dispatches (sm_timing_enable).
+struct SmTiming {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // pairs: 2 q, 2 q + 1
+    std::vector<int> kernel;     // kernel id of pair q
+    int used = 0;
+    bool overflow = false;
+};
 
 struct sm_plan {
     int device;
@@ -25,6 +35,7 @@ struct sm_plan {
     double2 *d_trig;
     double *d_tau;
     int64_t n_vox, n_rays;
+    SmTiming *tm;
 };
 
 // Views per record chunk: keep the records of one chunk near 1 GiB.
@@ -61,6 +72,42 @@ sm_status check_device(const sm_plan *p)
     if (dev != p->device)
         return fail(SM_EINVAL, "plan was created on device %d but device %d is current", p->device, dev);
     return SM_OK;
+}
+
+const int kTimingPairs = 4096;
+
+void timing_release(SmTiming *t)
+{
+    for (hipEvent_t e : t->ev) hipEventDestroy(e);
+    t->ev.clear();
+    t->kernel.clear();
+    t->used = 0;
+    t->overflow = false;
+    t->on = false;
+}
+
+// Records the opening event of a timed dispatch; returns its pair index or -1.
+int tm_begin(const sm_plan *p, int kernel, hipStream_t st)
+{
+    SmTiming *t = p->tm;
+    std::lock_guard<std::mutex> lk(t->mu);
+    if (!t->on) return -1;
+    if (t->used >= kTimingPairs) {
+        t->overflow = true;
+        return -1;
+    }
+    const int q = t->used++;
+    t->kernel[q] = kernel;
+    hipEventRecord(t->ev[2 * q], st);
+    return q;
+}
+
+void tm_end(const sm_plan *p, int q, hipStream_t st)
+{
+    if (q < 0) return;
+    SmTiming *t = p->tm;
+    std::lock_guard<std::mutex> lk(t->mu);
+    hipEventRecord(t->ev[2 * q + 1], st);
 }
 
 // Widest detector-column span of any adjoint tile (tw x th pixels) over all
@@ -185,10 +232,16 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
     p->prec = precision;
     p->n_vox = n_vox;
     p->n_rays = n_rays;
+    p->tm = new (std::nothrow) SmTiming();
+    if (!p->tm) {
+        delete p;
+        return fail(SM_ENOMEM, "host allocation");
+    }
     e = hipMalloc(&p->d_trig, sizeof(double2) * g->n_p);
     if (e == hipSuccess) e = hipMalloc(&p->d_tau, sizeof(double) * (G.nv + 1));
     if (e != hipSuccess) {
         hipFree(p->d_trig);
+        delete p->tm;
         delete p;
         return fail(SM_ENOMEM, "device tables: %s", hipGetErrorString(e));
     }
@@ -236,6 +289,7 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
     if (e != hipSuccess) {
         hipFree(p->d_trig);
         hipFree(p->d_tau);
+        delete p->tm;
         delete p;
         return hip_fail(e, "plan tables");
     }
@@ -246,6 +300,8 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
 sm_status sm_plan_destroy(sm_plan *p)
 {
     if (!p) return SM_OK;
+    timing_release(p->tm);
+    delete p->tm;
     hipFree(p->d_trig);
     hipFree(p->d_tau);
     delete p;
@@ -299,16 +355,26 @@ sm_status sm_forward(const sm_plan *p, const void *x, void *y, int32_t batch, vo
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = p->prec == SM_FP64;
     hipError_t e;
+    int q;
     if (p->G.dim == 2) {
+        q = tm_begin(p, SM_KERNEL_FORWARD, st);
         e = smk::launch_fwd2d(p->G, f64, x, y, batch, st);
+        tm_end(p, q, st);
     } else {
         const smk::RecLayout &RL = p->RL;
         double *P = (double *)((char *)ws + RL.data_off);
+        q = tm_begin(p, SM_KERNEL_PREFIX, st);
         e = smk::launch_prefix_columns(x, P, f64, batch, p->G.nz, p->G.ny, p->G.nx, st);
+        tm_end(p, q, st);
         for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
             const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
+            q = tm_begin(p, SM_KERNEL_RECORDS, st);
             e = smk::launch_records(p->G, RL, f64, v0, nvc, ws, st);
-            if (e == hipSuccess) e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, ws, P, y, batch, st);
+            tm_end(p, q, st);
+            if (e != hipSuccess) break;
+            q = tm_begin(p, SM_KERNEL_FORWARD, st);
+            e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, ws, P, y, batch, st);
+            tm_end(p, q, st);
         }
     }
     return e == hipSuccess ? SM_OK : hip_fail(e, "sm_forward launch");
@@ -322,22 +388,81 @@ sm_status sm_back(const sm_plan *p, const void *y, void *x, int32_t batch, void 
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = p->prec == SM_FP64;
     hipError_t e;
+    int q;
     if (p->G.dim == 2) {
+        q = tm_begin(p, SM_KERNEL_ADJOINT, st);
         e = smk::launch_back2d(p->G, f64, y, x, batch, st);
+        tm_end(p, q, st);
     } else {
         const smk::RecLayout &RL = p->RL;
         void *xt = (char *)ws + RL.data_off;
         e = hipSuccess;
         for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
             const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
+            q = tm_begin(p, SM_KERNEL_RECORDS, st);
             e = smk::launch_records(p->G, RL, f64, v0, nvc, ws, st);
-            if (e == hipSuccess)
-                e = smk::launch_back3d(p->G, p->L, RL, f64, v0, nvc, ws, y, xt, batch, v0 == 0, st);
+            tm_end(p, q, st);
+            if (e != hipSuccess) break;
+            q = tm_begin(p, SM_KERNEL_ADJOINT, st);
+            e = smk::launch_back3d(p->G, p->L, RL, f64, v0, nvc, ws, y, xt, batch, v0 == 0, st);
+            tm_end(p, q, st);
         }
-        if (e == hipSuccess)
+        if (e == hipSuccess) {
+            q = tm_begin(p, SM_KERNEL_TRANSPOSE, st);
             e = smk::launch_from_columns(xt, x, f64 ? 8 : 4, batch, p->G.nz, p->G.ny, p->G.nx, st);
+            tm_end(p, q, st);
+        }
     }
     return e == hipSuccess ? SM_OK : hip_fail(e, "sm_back launch");
+}
+
+sm_status sm_timing_enable(sm_plan *p, int32_t enable)
+{
+    if (!p) return fail(SM_EINVAL, "plan is NULL");
+    sm_status s = check_device(p);
+    if (s != SM_OK) return s;
+    SmTiming *t = p->tm;
+    std::lock_guard<std::mutex> lk(t->mu);
+    timing_release(t);
+    if (!enable) return SM_OK;
+    t->ev.assign(2 * kTimingPairs, nullptr);
+    t->kernel.assign(kTimingPairs, 0);
+    for (size_t i = 0; i < t->ev.size(); ++i) {
+        hipError_t e = hipEventCreate(&t->ev[i]);
+        if (e != hipSuccess) {
+            t->ev.resize(i);
+            timing_release(t);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    t->on = true;
+    return SM_OK;
+}
+
+sm_status sm_timing_read(sm_plan *p, sm_kernel_time *times_host)
+{
+    if (!p) return fail(SM_EINVAL, "plan is NULL");
+    if (!times_host) return fail(SM_EINVAL, "times_host is NULL");
+    SmTiming *t = p->tm;
+    std::lock_guard<std::mutex> lk(t->mu);
+    if (!t->on) return fail(SM_EINVAL, "timing is not enabled on this plan");
+    for (int k = 0; k < SM_KERNEL_COUNT; ++k) times_host[k] = sm_kernel_time{0, 0.0};
+    for (int q = 0; q < t->used; ++q) {
+        hipError_t e = hipEventSynchronize(t->ev[2 * q + 1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t->ev[2 * q], t->ev[2 * q + 1]);
+        if (e != hipSuccess) {
+            t->used = 0;
+            return hip_fail(e, "timing events");
+        }
+        times_host[t->kernel[q]].launches += 1;
+        times_host[t->kernel[q]].ms += (double)ms;
+    }
+    const bool over = t->overflow;
+    t->used = 0;
+    t->overflow = false;
+    if (over) return fail(SM_ERANGE, "more dispatches than timing events; the excess was not timed");
+    return SM_OK;
 }
 
 sm_status sm_footprints(const sm_plan *p, int32_t view, int32_t *boxes_host)

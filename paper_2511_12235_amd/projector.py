@@ -126,6 +126,19 @@ class SystemMatrix:
 
     __matmul__ = forward
 
+    # ----------------------------------------------------------------- timing
+    def timing(self, enable: bool = True):
+        """Switch per-kernel event timing on or off (sm_timing_enable)."""
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.lib().sm_timing_enable(self._plan, 1 if enable else 0), "sm_timing_enable")
+
+    def read_timing(self) -> dict:
+        """{kernel: (launches, ms)} since the last read (sm_timing_read)."""
+        arr = (_lib.SmKernelTime * len(_lib.KERNELS))()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.lib().sm_timing_read(self._plan, arr), "sm_timing_read")
+        return {name: (int(arr[i].launches), float(arr[i].ms)) for i, name in enumerate(_lib.KERNELS)}
+
     def weights_csr(self, values: str | None = None):
         """(row_ptr int64 [M+1], col_idx int32 [nnz], values [nnz]) on the host;
         the pattern is decided in FP64 (entries <= 1e-12 voxel measure drop)."""

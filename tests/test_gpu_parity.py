@@ -205,3 +205,29 @@ def test_nnz_count_beyond_2pow32_work_items():
                             (g.dy, g.dz), phi=g.phi[45:46])
     rows, _, _ = O.triplets(slab)
     assert count(slab) == len(rows)
+
+
+def test_kernel_timing_counts_dispatches():
+    """sm_timing_*: one timed interval per dispatch, none while disabled,
+    and reading clears the record."""
+    from paper_2511_12235_amd import _lib
+    g = GEOMS["cone_small"]
+    _say("kernel timing")
+    A = SystemMatrix(g, "fp32", device=DEV)
+    x = _t(wl.ellipse_phantom(g, 5, seed=3), "fp32")
+    ws = A.workspace(1)
+    with pytest.raises(_lib.SmError):
+        A.read_timing()
+    A.timing(True)
+    y = A.forward(x, ws=ws)
+    A.back(y, ws=ws)
+    t = A.read_timing()
+    assert t["prefix"][0] == 1 and t["transpose"][0] == 1
+    assert t["forward"][0] >= 1 and t["forward"][0] == t["adjoint"][0]
+    assert t["records"][0] == 2 * t["forward"][0]
+    assert all(ms > 0.0 for _, ms in t.values())
+    assert all(n == 0 for n, _ in A.read_timing().values())
+    A.timing(False)
+    A.forward(x, ws=ws)
+    with pytest.raises(_lib.SmError):
+        A.read_timing()
