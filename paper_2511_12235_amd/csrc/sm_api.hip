@@ -261,30 +261,43 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
             lds = 65536;
         L.lds_budget = lds < 65536 ? lds : 65536;
     }
-    const int tw[4] = {4, 4, 2, 2}, th[4] = {4, 2, 2, 1};
+    // adjoint tiles (tw x th pixels) of the four batch widths, then one pixel
+    const int tw[5] = {4, 4, 2, 2, 1}, th[5] = {4, 2, 2, 1, 1};
     for (int i = 0; i < 4; ++i) L.back_pcols[i] = 1;
+    L.rspan = 1;
     p->RL = smk::RecLayout{};
     if (e == hipSuccess && G.dim == 3) {
         int *d_span = nullptr;
-        e = hipMalloc(&d_span, sizeof(int) * 5);
-        if (e == hipSuccess) e = hipMemset(d_span, 0, sizeof(int) * 5);
-        for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+        e = hipMalloc(&d_span, sizeof(int) * 6);
+        if (e == hipSuccess) e = hipMemset(d_span, 0, sizeof(int) * 6);
+        for (int i = 0; i < 5 && e == hipSuccess; ++i) {
             const int64_t n = (int64_t)((G.nx + tw[i] - 1) / tw[i]) * ((G.ny + th[i] - 1) / th[i]) * G.n_p;
             hipLaunchKernelGGL(tile_span_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, G,
                                tw[i], th[i], d_span + i);
             e = hipGetLastError();
         }
-        if (e == hipSuccess) e = smk::launch_strip_count(G, d_span + 4, 0);
-        int span[5] = {1, 1, 1, 1, 1};
-        if (e == hipSuccess) e = hipMemcpy(span, d_span, sizeof(int) * 5, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = smk::launch_strip_count(G, d_span + 5, 0);
+        int span[6] = {1, 1, 1, 1, 1, 1};
+        if (e == hipSuccess) e = hipMemcpy(span, d_span, sizeof(int) * 6, hipMemcpyDeviceToHost);
         hipFree(d_span);
         for (int i = 0; i < 4; ++i) L.back_pcols[i] = span[i] > 0 ? span[i] : 1;
-        const int cap = span[4] > 0 ? span[4] : 1;
+        L.rspan = span[4] > 0 ? span[4] : 1;
+        const int cap = span[5] > 0 ? span[5] : 1;
         const size_t rsz = precision == SM_FP64 ? sizeof(smk::Rec<double>) : sizeof(smk::Rec<float>);
         const int64_t per_view = (int64_t)G.nu * cap * (int64_t)rsz;
         int64_t V = kRecordBudget / (per_view > 0 ? per_view : 1);
         V = V < 1 ? 1 : (V > G.n_p ? G.n_p : V);
         p->RL = smk::make_layout(cap, G.nx > G.ny ? G.nx : G.ny, (int)V, G.nu, G.nx, G.ny, rsz);
+        const size_t need = smk::back3d_lds_min(G, L, precision == SM_FP64);
+        if (e == hipSuccess && need > (size_t)L.lds_budget) {
+            hipFree(p->d_trig);
+            hipFree(p->d_tau);
+            delete p->tm;
+            delete p;
+            return fail(SM_EUNSUPPORTED,
+                        "detector footprint too wide: the adjoint needs %zu bytes of LDS per "
+                        "workgroup, %d available", need, L.lds_budget);
+        }
     }
     if (e != hipSuccess) {
         hipFree(p->d_trig);

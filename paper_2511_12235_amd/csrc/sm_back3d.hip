@@ -3,16 +3,19 @@
 // Voxel-stationary gather, no atomics: a workgroup owns a TX x TY tile of
 // pixels and every voxel above them (one lane per z index) and keeps the
 // tile's sums in registers while it loops over the views of a chunk.  Per
-// view it stages the detector columns the tile can meet (all rows, with a zero
-// row above and below) in LDS, then for every (pixel, column) strip record
-// (built by sm_rec.hip, found through the strip's per-major table and read
-// with scalar loads) lane iz finds the row planes p_first..p_last that cut its
-// voxel inside the strip and adds
-//     c A y[p_last] + sum_p H_p (y[p-1] - y[p]),   H_p = K_p(za) - K_p(zb),
-// which is  sum_r (H_{r+1} - H_r) y[r]  summed by parts over the rows; H_p is
-// the volume of the voxel below plane p (sm_common.h).  Chunks of views add
-// into the z-contiguous workspace in a fixed order, which is transposed to the
-// caller's layout afterwards.
+// view it stages in LDS the detector columns the tile can meet (all rows, with
+// a zero row above and below) and the strip records of the tile's pixels
+// (built by sm_rec.hip).  For every (pixel, column) record lane iz then adds
+//     sum_q (K_q(za) - K_q(zb)) (y[q-1] - y[q]),
+// the by-parts form of sum_r W_r y[r] over the rows, where K_q(z) is the
+// volume of the strip column above height z and below row plane q
+// (sm_common.h) and za / zb are the voxel's bottom and top faces.  Planes
+// wholly below the voxel add nothing; planes wholly above it add c A each,
+// which telescopes to c A y[first such plane - 1].  Of the planes reaching
+// into the voxel, those wholly above za contribute the linear volume
+// A (tau lbar - za) at za; only planes straddling a face need the chord
+// table.  Chunks of views add into the z-contiguous workspace in a fixed
+// order, which is transposed to the caller's layout afterwards.
 #include "sm_internal.h"
 
 namespace smk {
@@ -22,18 +25,23 @@ __global__ void __launch_bounds__(1024)
 back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict__ recs,
               const int *__restrict__ sj0, const int *__restrict__ soff,
               const int2 *__restrict__ pixk, const T *__restrict__ y, T *__restrict__ xt, int B,
-              int b0, int pcols, int first)
+              int b0, int pcols, int rspan, int first)
 {
     constexpr int TP = TX * TY;
+    constexpr int RCH = (int)(sizeof(Rec<T>) / 16);  // 16-byte chunks per record
     extern __shared__ __align__(16) unsigned char smem[];
     const int nthr = blockDim.x, tid = threadIdx.x;
     const int nz = G.nz, nv = G.nv;
     const int rowstride = nv + 2;
 
-    double *ptau = reinterpret_cast<double *>(smem);
-    T *ptf = reinterpret_cast<T *>(smem + sizeof(double) * (nv + 1));
+    // LDS: staged records | plane tables | detector patch
+    Rec<T> *rtab = reinterpret_cast<Rec<T> *>(smem);
+    size_t off = sizeof(Rec<T>) * (size_t)TP * rspan;
+    double *ptau = reinterpret_cast<double *>(smem + off);
+    off += sizeof(double) * (nv + 1);
+    T *ptf = reinterpret_cast<T *>(smem + off);
     T *pinv = ptf + (nv + 1);
-    size_t off = sizeof(double) * (nv + 1) + 2 * sizeof(T) * (nv + 1);
+    off += 2 * sizeof(T) * (nv + 1);
     off = (off + 15) & ~(size_t)15;
     T *patch = reinterpret_cast<T *>(smem + off);
 
@@ -53,11 +61,9 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
     const int iz = tid;
     const bool active = iz < nz;
     const double za = G.z0 + (double)iz * G.c;
-    const double zb = za + G.c;
-    const float fza = (float)za, fzb = (float)zb;
+    const double zb = G.z0 + (double)(iz + 1) * G.c;
     const T cT = T(G.c);
-    const float inv_dv = (float)(1.0 / G.dv);
-    const float fD = (float)G.D, fv0 = (float)G.v0;
+    const T tDdv = T(G.D / G.dv), v0dv = T(G.v0 / G.dv);
 
     T acc[TP][NBAT];
 #pragma unroll
@@ -80,7 +86,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
             if (ix < G.nx && iy < G.ny) {
                 const int2 q = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
                 kk0[p] = q.x;
-                kk1[p] = q.y;
+                kk1[p] = min(q.y, q.x + rspan - 1);  // rspan bounds every pixel's span
                 if (q.y >= q.x) {
                     kmin = min(kmin, q.x);
                     kmax = max(kmax, q.y);
@@ -88,9 +94,9 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
             }
         }
         if (kmax < kmin) continue;
-        if (kmax - kmin + 1 > pcols) kmax = kmin + pcols - 1;  // bound from the plan
+        if (kmax - kmin + 1 > pcols) kmax = kmin + pcols - 1;  // pcols bounds every tile's span
         const int pc = kmax - kmin + 1;
-        __syncthreads();  // previous view's patch is consumed
+        __syncthreads();  // the previous view's patch and records are consumed
         // --- stage y[view][:, kmin..kmax] with zero rows at -1 and nv
         {
             const float inv_pc = 1.0f / (float)pc;
@@ -109,6 +115,24 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
                 }
             }
         }
+        // --- stage the strip records of the tile's pixels in slot (p, k - kk0[p])
+        for (int q = tid; q < TP * rspan * RCH; q += nthr) {
+            const int p = q / (rspan * RCH);
+            const int rem = q - p * rspan * RCH;
+            const int kk = rem / RCH, ch = rem - kk * RCH;
+            const int ix = ix0 + p % TX, iy = iy0 + p / TX;
+            if (ix >= G.nx || iy >= G.ny) continue;
+            const int2 kr = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
+            const int k = kr.x + kk;
+            if (k > kr.y || k < kmin || k > kmax) continue;
+            const int64_t strip = (int64_t)vl * G.nu + k;
+            const int pos = strip_position(ax.major_x, ix, iy, sj0 + strip * RL.n_major_max,
+                                           soff + strip * (RL.n_major_max + 1));
+            if (pos < 0) continue;
+            const uint4 *src = reinterpret_cast<const uint4 *>(recs + strip * RL.cap + pos);
+            uint4 *dst = reinterpret_cast<uint4 *>(rtab + p * rspan + kk);
+            dst[ch] = src[ch];
+        }
         __syncthreads();
         if (!active) continue;
 #pragma unroll
@@ -122,48 +146,11 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
                 const Rec<T> &R = recs[strip * RL.cap + pos];
                 const int n = R.n;
                 if (n == 0) continue;
-                const double lmin = R.lc + (double)R.tab[0][0];
-                const double lmax = R.lc + (double)R.tab[n - 1][0];
-                // row planes cutting the voxel inside the strip: estimate the
-                // index where a plane's highest point reaches za (lowest point
-                // reaches zb), then settle it with exact FP64 comparisons
-                const float tst = fza / (float)(za >= 0.0 ? lmax : lmin);
-                int pf = (int)fminf(fmaxf(floorf((tst * fD - fv0) * inv_dv) + 1.0f, 0.0f), (float)(nv + 1));
-                while (pf > 0) {
-                    const double t = ptau[pf - 1];
-                    if (t * (t >= 0.0 ? lmax : lmin) > za) --pf; else break;
-                }
-                while (pf <= nv) {
-                    const double t = ptau[pf];
-                    if (!(t * (t >= 0.0 ? lmax : lmin) > za)) ++pf; else break;
-                }
-                const float tss = fzb / (float)(zb >= 0.0 ? lmin : lmax);
-                int pl = (int)fminf(fmaxf(ceilf((tss * fD - fv0) * inv_dv) - 1.0f, -1.0f), (float)nv);
-                while (pl < nv) {
-                    const double t = ptau[pl + 1];
-                    if (t * (t >= 0.0 ? lmin : lmax) < zb) ++pl; else break;
-                }
-                while (pl >= 0) {
-                    const double t = ptau[pl];
-                    if (!(t * (t >= 0.0 ? lmin : lmax) < zb)) --pl; else break;
-                }
-                const T cA = cT * R.tab[0][2];
+                const StripTab<T> S = strip_tab<T>(R.tab, rtab[p * rspan + (k - kk0[p])].tab);
                 const T *Y = patch + (size_t)(k - kmin) * rowstride + 1;  // Y[-1] .. Y[nv]
                 T sum[NBAT];
-#pragma unroll
-                for (int b = 0; b < NBAT; ++b)
-                    sum[b] = (pl >= 0 && pl < nv) ? cA * Y[(size_t)b * pcols * rowstride + pl] : T(0);
-                for (int q = pf; q <= pl; ++q) {
-                    const double ea = ptau[q] * R.lc - za;
-                    const T Ha = eval_K<T>(R.tab, n, ptf[q], pinv[q], T(ea));
-                    const T Hb = eval_K<T>(R.tab, n, ptf[q], pinv[q], T(ea - G.c));
-                    const T Hv = Ha - Hb;
-#pragma unroll
-                    for (int b = 0; b < NBAT; ++b) {
-                        const T *Yb = Y + (size_t)b * pcols * rowstride;
-                        sum[b] += Hv * (Yb[q - 1] - Yb[q]);
-                    }
-                }
+                adj_terms<T, NBAT>(S, R.lc, R.tab[n - 1][0], ptau, ptf, pinv, za, zb, tDdv, v0dv,
+                                   nv, cT, Y, (size_t)pcols * rowstride, sum);
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) acc[p][b] += sum[b];
             }
@@ -189,7 +176,8 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
 template <typename T, int NBAT, int TX, int TY>
 static size_t back3d_lds(const DevGeom &G, const LaunchCfg &L, int slot)
 {
-    size_t lds = sizeof(double) * (G.nv + 1) + 2 * sizeof(T) * (G.nv + 1);
+    size_t lds = sizeof(Rec<T>) * (size_t)TX * TY * L.rspan;
+    lds += sizeof(double) * (G.nv + 1) + 2 * sizeof(T) * (G.nv + 1);
     lds = (lds + 15) & ~(size_t)15;
     lds += sizeof(T) * (size_t)NBAT * L.back_pcols[slot] * (G.nv + 2);
     return lds;
@@ -205,7 +193,7 @@ static hipError_t launch_back3d_t(const DevGeom &G, const LaunchCfg &L, const Re
     const int ntx = (G.nx + TX - 1) / TX, nty = (G.ny + TY - 1) / TY;
     hipLaunchKernelGGL((back3d_kernel<T, NBAT, TX, TY>), dim3(ntx * nty), dim3(L.back_threads), lds,
                        st, G, RL, v0, nvc, (const Rec<T> *)RP.recs, RP.sj0, RP.soff, RP.pixk, y, xt,
-                       B, b0, L.back_pcols[slot], first ? 1 : 0);
+                       B, b0, L.back_pcols[slot], L.rspan, first ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -228,6 +216,11 @@ static hipError_t launch_back3d_all(const DevGeom &G, const LaunchCfg &L, const 
         else { e = launch_back3d_t<T, 1, 4, 4>(G, L, RL, 0, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 1; }
     }
     return e;
+}
+
+size_t back3d_lds_min(const DevGeom &G, const LaunchCfg &L, bool fp64)
+{
+    return fp64 ? back3d_lds<double, 1, 4, 4>(G, L, 0) : back3d_lds<float, 1, 4, 4>(G, L, 0);
 }
 
 hipError_t launch_back3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,

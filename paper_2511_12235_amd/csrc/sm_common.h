@@ -283,6 +283,191 @@ __host__ __device__ inline T eval_K(const T (*tab)[4], int n, T tau, T inv_tau, 
 }
 
 // ---------------------------------------------------------------------------
+// classification of row planes against faces for one strip record
+// ---------------------------------------------------------------------------
+// Over the strip, plane z = tau l spans heights [lo, hi] with
+// lo = tau Llo, hi = tau Lhi for tau >= 0 (swapped for tau < 0), Llo / Lhi
+// being the nearest / farthest depth of the strip polygon.  Against a face at
+// height z a plane is wholly below (K = 0), wholly above (K = the linear
+// integral A (tau lbar - z), lbar the area-weighted mean depth) or straddles
+// it (K from the chord table).  Both walks below only need the split to be
+// consistent: K_cut is exact for a plane anywhere, and a plane put on the
+// wrong side of a face by rounding is off by a volume of rounding size.
+
+// Row planes: indices < ph lie wholly below z, indices >= pa wholly above.
+// tau_q = (v0 + q dv) / D, kLo = D / (Llo dv), kHi = D / (Lhi dv).
+template <typename T>
+__host__ __device__ inline void plane_split(T z, T kLo, T kHi, T v0dv, int nv, int &ph, int &pa)
+{
+    const bool up = z >= T(0);
+    const T xh = z * (up ? kHi : kLo) - v0dv;  // hi(q) = z at this index
+    const T xl = z * (up ? kLo : kHi) - v0dv;  // lo(q) = z at this index
+    const T top = T(nv + 1);
+    T fh = floor(xh) + T(1), fl = ceil(xl);
+    fh = fh < T(0) ? T(0) : (fh > top ? top : fh);
+    fl = fl < T(0) ? T(0) : (fl > top ? top : fl);
+    ph = (int)fh;
+    pa = (int)fl;
+}
+
+// Voxel faces z_j = z0 + j c against one plane of extent [lo, hi]: faces
+// < fa lie wholly below the plane, faces >= fb wholly above it.
+template <typename T>
+__host__ __device__ inline void face_split(T lo, T hi, T inv_c, T z0c, int nz, int &fa, int &fb)
+{
+    const T top = T(nz + 1);
+    T a = floor(lo * inv_c - z0c) + T(1), b = ceil(hi * inv_c - z0c);
+    a = a < T(0) ? T(0) : (a > top ? top : a);
+    b = b < T(0) ? T(0) : (b > top ? top : b);
+    fa = (int)a;
+    fb = (int)b;
+}
+
+// The uniform part of a strip record used by K_cut; `tab` points at the
+// chord table (an LDS copy in the kernels).
+template <typename T>
+struct StripTab {
+    const T (*tab)[4];
+    T d0, A, S1, b1, b2, b3, b4;  // nearest depth, area, first moment, interior breakpoints
+};
+
+template <typename T>
+__host__ __device__ inline StripTab<T> strip_tab(const T (*tab)[4], const T (*rows)[4])
+{
+    StripTab<T> S;
+    S.tab = rows;
+    S.d0 = tab[0][0];
+    S.A = tab[0][2];
+    S.S1 = tab[0][3];
+    S.b1 = tab[1][0];
+    S.b2 = tab[2][0];
+    S.b3 = tab[3][0];
+    S.b4 = tab[4][0];
+    return S;
+}
+
+// K = integral over P of (e + tau l')_+ dA for any plane (see eval_K).  The
+// segment of the breakpoint table holding lam = -e / tau is found by
+// counting breakpoints; Psi continues linearly below the nearest depth
+// (Psi(lam) = S1 + (d0 - lam) A there) and is zero beyond the farthest, so
+// the result is exact wherever the plane lies.
+template <typename T>
+__host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
+{
+    if (tau == T(0)) return e > T(0) ? e * S.A : T(0);
+    const T lam = -e * inv_tau;
+    const int j = (lam >= S.b1 ? 1 : 0) + (lam >= S.b2 ? 1 : 0) + (lam >= S.b3 ? 1 : 0) +
+                  (lam >= S.b4 ? 1 : 0);
+    const T *r0 = S.tab[j];
+    const T *r1 = S.tab[j + 1];
+    const T dA = r0[0], w0 = r0[1];
+    const T dB = r1[0], w1 = r1[1], s0 = r1[2], s1 = r1[3];
+    const T L = dB - dA;
+    T h = dB - lam;
+    h = h < T(0) ? T(0) : (h > L ? L : h);
+    const T wl = w1 + (w0 - w1) * (L > T(0) ? h * rcp_(L) : T(0));
+    T psi = h * h * (wl * T(1.0 / 6.0) + w1 * T(1.0 / 3.0)) + s1 + h * s0;
+    const T below = S.d0 - lam;
+    psi += (below > T(0) ? below : T(0)) * S.A;
+    if (tau > T(0)) return tau * psi;
+    return (-tau) * (psi - S.S1 + (lam - S.d0) * S.A);
+}
+
+// Heights of plane tau over the strip [Llo, Lhi] (depths).
+template <typename T>
+__host__ __device__ inline void plane_extent(T tau, T Llo, T Lhi, T &lo, T &hi)
+{
+    const T a = tau * Llo, b = tau * Lhi;
+    lo = tau >= T(0) ? a : b;
+    hi = tau >= T(0) ? b : a;
+}
+
+// G_p of one plane for one strip record; f_out = first voxel not wholly below.
+template <typename T, int NBAT>
+__host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, double lc,
+                                        double lbar, T Llo, T Lhi, double tau, T tauf, T invt,
+                                        T inv_c, T z0c, const double *const (&Pc)[NBAT], int &f_out,
+                                        T (&gs)[NBAT])
+{
+    const int nz = G.nz;
+    T lo, hi;
+    plane_extent<T>(tauf, Llo, Lhi, lo, hi);
+    int fa, fb;
+    face_split<T>(lo, hi, inv_c, z0c, nz, fa, fb);
+    const int f = fa - 1 < 0 ? 0 : (fa - 1 > nz ? nz : fa - 1);
+    f_out = f;
+#pragma unroll
+    for (int b = 0; b < NBAT; ++b) gs[b] = T(0);
+    double Pm[NBAT], P0[NBAT];  // P[j - 1], P[j] along the straddle walk
+    if (fa >= 1 && fa <= nz) {  // face f wholly below the plane: linear volume
+        const T K = S.A * T(tau * lbar - (G.z0 + (double)f * G.c));
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) {
+            Pm[b] = Pc[b][f];
+            P0[b] = Pc[b][f + 1];
+            gs[b] = K * T(P0[b] - Pm[b]);
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) Pm[b] = P0[b] = Pc[b][fa > nz ? nz : 0];
+    }
+    const int je = fb - 1 < nz ? fb - 1 : nz;
+    for (int j = fa; j <= je; ++j) {  // straddled faces
+        const T e = T(tau * lc - (G.z0 + (double)j * G.c));
+        const T K = K_cut<T>(S, tauf, invt, e);
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) {
+            const double Pn = j < nz ? Pc[b][j + 1] : P0[b];
+            const T xj = T(Pn - P0[b]);
+            const T xm = j >= 1 ? T(P0[b] - Pm[b]) : T(0);
+            gs[b] += K * (xj - xm);
+            Pm[b] = P0[b];
+            P0[b] = Pn;
+        }
+    }
+}
+
+// One strip record's contribution to voxel [za, zb] of its column in the
+// adjoint: sum_q (K_q(za) - K_q(zb)) (y[q-1] - y[q]) with y[-1] = y[nv] = 0.
+// Y[b * ystride + q] holds y[q] of batch element b for q in [-1, nv];
+// ptau / ptf / pinv are the plane slopes in FP64, in T and their inverses.
+template <typename T, int NBAT>
+__host__ __device__ inline void adj_terms(const StripTab<T> &S, double lc, T dn,
+                                          const double *ptau, const T *ptf, const T *pinv,
+                                          double za, double zb, T tDdv, T v0dv, int nv, T cT,
+                                          const T *Y, size_t ystride, T (&sum)[NBAT])
+{
+    const T kLo = tDdv / T(lc + (double)S.d0);
+    const T kHi = tDdv / T(lc + (double)dn);
+    const double lbar = lc + (double)(S.d0 + S.S1 / S.A);  // area-weighted mean depth
+    int pha, paa, phb, pab;
+    plane_split<T>(T(za), kLo, kHi, v0dv, nv, pha, paa);
+    plane_split<T>(T(zb), kLo, kHi, v0dv, nv, phb, pab);
+    // planes from pab up lie wholly above the voxel: c A each, telescoped
+    const T cA = cT * S.A;
+#pragma unroll
+    for (int b = 0; b < NBAT; ++b) sum[b] = cA * Y[b * ystride + pab - 1];
+    // planes wholly above za that reach below zb: linear volume at za
+    for (int q = paa; q < pab; ++q) {
+        const T K = S.A * T(ptau[q] * lbar - za);
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) sum[b] += K * (Y[b * ystride + q - 1] - Y[b * ystride + q]);
+    }
+    // planes straddling za (+K) or zb (-K), one merged loop
+    const int na = paa > pha ? paa - pha : 0;
+    const int nb = pab > phb ? pab - phb : 0;
+    for (int t = 0; t < na + nb; ++t) {
+        const bool top = t >= na;
+        const int q = top ? phb + (t - na) : pha + t;
+        const double e = ptau[q] * lc - (top ? zb : za);
+        const T K = K_cut<T>(S, ptf[q], pinv[q], T(e));
+        const T Ks = top ? -K : K;
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) sum[b] += Ks * (Y[b * ystride + q - 1] - Y[b * ystride + q]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 2D: area of the pixel on the u <= u* side (the paper's sweep of Sec. III-B)
 // ---------------------------------------------------------------------------
 // The boundary ray of detector coordinate u* is t' - mu l' + eps = 0 in local

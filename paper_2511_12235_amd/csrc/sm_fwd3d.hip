@@ -4,73 +4,25 @@
 // meets; on the GPU that would need atomics, so the loop is turned inside out.
 // One workgroup owns one (view, detector column k) and one lane owns detector
 // row r and its lower row plane r.  The workgroup walks the strip records of
-// column k (built by sm_rec.hip; uniform, so they are read with scalar loads)
-// and, for each pixel, lane r adds
-//     c A * sum_{iz in [f_r, f_{r+1})} x_iz  +  G_{r+1} - G_r,
-// where A is the strip area, f_p the first voxel of the column not entirely
-// below plane p, and G_p the x-weighted volume below plane p of the voxels
-// plane p cuts.  By parts over the voxel faces z_j,
-//     G_p = sum_j (x_j - x_{j-1}) K_p(z_j),
-// K_p(z) being the volume of the strip column above z and below plane p
-// (sm_common.h); only faces the plane crosses inside the strip need the
-// piecewise evaluation, the others are linear or zero.  Voxel sums come from
-// FP64 prefix sums along z, so the range sum is a single difference.  Lane r
-// keeps  c A R - G_r  and  G_r  apart; the G of the plane above is added once
-// at the end through LDS.  The top detector edge (plane nv) has no lane: its G
-// is summed lane-parallel over the strip's pixels and reduced in a fixed order.
+// column k (built by sm_rec.hip; staged in LDS in chunks) and, for each pixel,
+// lane r adds V_{r+1} - V_r, where V_p is the x-weighted volume of the pixel's
+// voxel column below plane p:
+//     V_p = c A sum_{iz < f} x_iz  +  G_p,
+// f being the first voxel not wholly below the plane.  By parts over the
+// voxel faces z_j, G_p = sum_j K_p(z_j) (x_j - x_{j-1}) over the faces from
+// z_f up, K_p(z) the volume of the strip column above z and below plane p
+// (sm_common.h).  Face z_f lies wholly below the plane, so K_p(z_f) is the
+// linear volume A (tau lbar - z_f); faces the plane straddles need the chord
+// table; faces wholly above it add nothing.  Voxel sums come from FP64 prefix
+// sums along z, so c A (V_{r+1} - V_r) needs one difference.  Lane r keeps
+// c A (range sum) - G_r and G_r apart; the G of the plane above is added once
+// at the end through LDS.  The top detector edge (plane nv) has no lane: its
+// G is summed lane-parallel over the strip's pixels in a fixed order.
 #include "sm_internal.h"
 
 namespace smk {
 
-template <typename T, int NBAT>
-__device__ __forceinline__ void plane_terms(const DevGeom &G, const Rec<T> &R, int n, double tau,
-                                            T tauf, T invt, double inv_c, double zoff,
-                                            const double *const (&Pc)[NBAT], bool want_range,
-                                            double tau_next, T (&rs)[NBAT], T (&gs)[NBAT])
-{
-    const T d0 = R.tab[0][0], dn = R.tab[n - 1][0];
-    const double lmin = R.lc + (double)d0, lmax = R.lc + (double)dn;
-    const bool neg = tau < 0.0;
-    const double lo_abs = tau * (neg ? lmax : lmin), hi_abs = tau * (neg ? lmin : lmax);
-    const int f = (int)dmin_(dmax_(floor(lo_abs * inv_c - zoff), 0.0), (double)G.nz);
-    const int l = (int)dmin_(dmax_(floor(hi_abs * inv_c - zoff), -1.0), (double)(G.nz - 1));
-    double Pprev[NBAT];
-#pragma unroll
-    for (int b = 0; b < NBAT; ++b) Pprev[b] = Pc[b][f];
-    if (want_range) {
-        const double lo1 = tau_next * (tau_next < 0.0 ? lmax : lmin);
-        const int f1 = (int)dmin_(dmax_(floor(lo1 * inv_c - zoff), 0.0), (double)G.nz);
-#pragma unroll
-        for (int b = 0; b < NBAT; ++b) rs[b] = T(Pc[b][f1] - Pprev[b]);
-    }
-    const double hz = tau * R.lc - G.z0;  // plane height above z0 at the pixel centre
-    T xprev[NBAT];
-#pragma unroll
-    for (int b = 0; b < NBAT; ++b) {
-        xprev[b] = T(0);
-        gs[b] = T(0);
-    }
-    for (int j = f; j <= l + 1; ++j) {
-        T xcur[NBAT];
-#pragma unroll
-        for (int b = 0; b < NBAT; ++b) xcur[b] = T(0);
-        if (j <= l) {
-#pragma unroll
-            for (int b = 0; b < NBAT; ++b) {
-                const double pn = Pc[b][j + 1];
-                xcur[b] = T(pn - Pprev[b]);
-                Pprev[b] = pn;
-            }
-        }
-        const T e = T(hz - (double)j * G.c);
-        const T Kv = eval_K<T>(R.tab, n, tauf, invt, e);
-#pragma unroll
-        for (int b = 0; b < NBAT; ++b) {
-            gs[b] += (xcur[b] - xprev[b]) * Kv;
-            xprev[b] = xcur[b];
-        }
-    }
-}
+constexpr int kFwdChunk = 64;  // strip records staged in LDS at a time
 
 template <typename T, int NBAT>
 __global__ void __launch_bounds__(1024)
@@ -78,10 +30,12 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
              const int *__restrict__ soff, const double *__restrict__ P, T *__restrict__ y, int B,
              int b0)
 {
+    constexpr int RCH = (int)(sizeof(Rec<T>) / 16);
     extern __shared__ __align__(16) unsigned char smem[];
     const int nthr = blockDim.x, tid = threadIdx.x;
-    T *ex = reinterpret_cast<T *>(smem);          // (nthr + 1) * NBAT
-    T *red = ex + (size_t)(nthr + 1) * NBAT;      // nthr * NBAT
+    Rec<T> *rbuf = reinterpret_cast<Rec<T> *>(smem);                                // kFwdChunk
+    T *ex = reinterpret_cast<T *>(smem + sizeof(Rec<T>) * kFwdChunk);               // (nthr + 1) * NBAT
+    T *red = ex + (size_t)(nthr + 1) * NBAT;                                        // nthr * NBAT
     const int nz = G.nz, nv = G.nv;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int vl = lb / G.nu, k = lb - vl * G.nu;
@@ -91,7 +45,7 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     const int64_t strip = (int64_t)vl * G.nu + k;
     const int n_ent = soff[strip * (RL.n_major_max + 1) + ax.n_major];
     const Rec<T> *Rs = recs + strip * RL.cap;
-    const double inv_c = 1.0 / G.c, zoff = G.z0 * inv_c;
+    const T inv_c = T(1.0 / G.c), z0c = T(G.z0 / G.c);
     const T cT = T(G.c);
     const size_t colstride = (size_t)(nz + 1);
 
@@ -99,52 +53,72 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     const int r = tid;
     const bool active = r < nv;
     const double tau0 = active ? G.tau[r] : 0.0;
-    const double tau1 = active ? G.tau[r + 1] : 0.0;
-    const T tf0 = T(tau0);
+    const T tf0 = T(tau0), tf1 = T(active ? G.tau[r + 1] : 0.0);
     const T inv0 = tf0 != T(0) ? T(1) / tf0 : T(0);
+    const double tauT = G.tau[nv];
+    const T tfT = T(tauT);
+    const T invT = tfT != T(0) ? T(1) / tfT : T(0);
 
-    T acc1[NBAT], acc2[NBAT];
+    T acc1[NBAT], acc2[NBAT], accT[NBAT];
 #pragma unroll
-    for (int b = 0; b < NBAT; ++b) acc1[b] = acc2[b] = T(0);
+    for (int b = 0; b < NBAT; ++b) acc1[b] = acc2[b] = accT[b] = T(0);
 
-    for (int e = 0; e < n_ent; ++e) {
-        const Rec<T> &R = Rs[e];
-        const int n = R.n;
-        if (n == 0) continue;
+    for (int c0 = 0; c0 < n_ent; c0 += kFwdChunk) {
+        const int cnt = n_ent - c0 < kFwdChunk ? n_ent - c0 : kFwdChunk;
+        __syncthreads();  // previous chunk consumed
+        {
+            const uint4 *src = reinterpret_cast<const uint4 *>(Rs + c0);
+            uint4 *dst = reinterpret_cast<uint4 *>(rbuf);
+            for (int q = tid; q < cnt * RCH; q += nthr) dst[q] = src[q];
+        }
+        __syncthreads();
         if (active) {
-            const double *Pc[NBAT];
+            for (int e = 0; e < cnt; ++e) {
+                const Rec<T> &R = Rs[c0 + e];  // uniform fields through the scalar cache
+                const int n = R.n;
+                if (n == 0) continue;
+                const StripTab<T> S = strip_tab<T>(R.tab, rbuf[e].tab);
+                const double lc = R.lc;
+                const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
+                const double lbar = lc + (double)(S.d0 + S.S1 / S.A);
+                const double *Pc[NBAT];
 #pragma unroll
-            for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;
-            T rs[NBAT], gs[NBAT];
-            plane_terms<T, NBAT>(G, R, n, tau0, tf0, inv0, inv_c, zoff, Pc, true, tau1, rs, gs);
-            const T cA = cT * R.tab[0][2];
+                for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;
+                int f;
+                T gs[NBAT];
+                plane_G<T, NBAT>(G, S, lc, lbar, Llo, Lhi, tau0, tf0, inv0, inv_c, z0c, Pc, f, gs);
+                // first voxel not wholly below plane r + 1, as its own lane finds it
+                T lo1, hi1;
+                plane_extent<T>(tf1, Llo, Lhi, lo1, hi1);
+                int fa1, fb1;
+                face_split<T>(lo1, hi1, inv_c, z0c, nz, fa1, fb1);
+                const int f1 = fa1 - 1 < 0 ? 0 : (fa1 - 1 > nz ? nz : fa1 - 1);
+                const T cA = cT * S.A;
 #pragma unroll
-            for (int b = 0; b < NBAT; ++b) {
-                acc1[b] += cA * rs[b] - gs[b];
-                acc2[b] += gs[b];
+                for (int b = 0; b < NBAT; ++b) {
+                    acc1[b] += cA * T(Pc[b][f1] - Pc[b][f]) - gs[b];
+                    acc2[b] += gs[b];
+                }
             }
         }
-    }
-
-    // top detector edge (plane nv): lane-parallel over the strip's pixels
-    T accT[NBAT];
-#pragma unroll
-    for (int b = 0; b < NBAT; ++b) accT[b] = T(0);
-    {
-        const double tauT = G.tau[nv];
-        const T tfT = T(tauT);
-        const T invT = tfT != T(0) ? T(1) / tfT : T(0);
-        for (int e = tid; e < n_ent; e += nthr) {
-            const Rec<T> &R = Rs[e];
+        // top detector edge: lane e takes record c0 + e (fields from LDS)
+        if (tid < cnt) {
+            const Rec<T> &R = rbuf[tid];
             const int n = R.n;
-            if (n == 0) continue;
-            const double *Pc[NBAT];
+            if (n > 0) {
+                const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
+                const double lc = R.lc;
+                const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
+                const double lbar = lc + (double)(S.d0 + S.S1 / S.A);
+                const double *Pc[NBAT];
 #pragma unroll
-            for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;
-            T rs[NBAT], gs[NBAT];
-            plane_terms<T, NBAT>(G, R, n, tauT, tfT, invT, inv_c, zoff, Pc, false, 0.0, rs, gs);
+                for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;
+                int f;
+                T gs[NBAT];
+                plane_G<T, NBAT>(G, S, lc, lbar, Llo, Lhi, tauT, tfT, invT, inv_c, z0c, Pc, f, gs);
 #pragma unroll
-            for (int b = 0; b < NBAT; ++b) accT[b] += gs[b];
+                for (int b = 0; b < NBAT; ++b) accT[b] += gs[b];
+            }
         }
     }
 
@@ -177,11 +151,18 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
 }
 
 template <typename T, int NBAT>
+static size_t fwd3d_lds(const LaunchCfg &L)
+{
+    return sizeof(Rec<T>) * kFwdChunk + sizeof(T) * (size_t)(2 * L.fwd_threads + 1) * NBAT;
+}
+
+template <typename T, int NBAT>
 static hipError_t launch_fwd3d_t(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, int v0,
                                  int nvc, const Rec<T> *recs, const int *soff, const double *P,
                                  T *y, int B, int b0, hipStream_t st)
 {
-    const size_t lds = sizeof(T) * (size_t)(2 * L.fwd_threads + 1) * NBAT;
+    const size_t lds = fwd3d_lds<T, NBAT>(L);
+    if (lds > (size_t)L.lds_budget) return hipErrorInvalidValue;
     hipLaunchKernelGGL((fwd3d_kernel<T, NBAT>), dim3(nvc * G.nu), dim3(L.fwd_threads), lds, st, G,
                        RL, v0, recs, soff, P, y, B, b0);
     return hipGetLastError();

@@ -14,6 +14,7 @@ struct LaunchCfg {
     int fwd_threads;   // 64 * ceil(nv / 64)
     int back_threads;  // 64 * ceil(nz / 64)
     int back_pcols[4]; // detector columns an adjoint tile can meet (max over views)
+    int rspan;         // detector columns a single pixel can meet (max over views)
     int lds_budget;    // dynamic LDS bytes a workgroup may use
 };
 
@@ -83,6 +84,8 @@ hipError_t launch_fwd3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &R
 hipError_t launch_back3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,
                          int v0, int nvc, void *ws, const void *y, void *xt, int B, bool first,
                          hipStream_t st);
+// LDS bytes of the smallest adjoint configuration (single batch element).
+size_t back3d_lds_min(const DevGeom &G, const LaunchCfg &L, bool fp64);
 hipError_t launch_fwd2d(const DevGeom &G, bool fp64, const void *x, void *y, int B,
                         hipStream_t st);
 hipError_t launch_back2d(const DevGeom &G, bool fp64, const void *y, void *x, int B,
