@@ -144,6 +144,60 @@ sm_status sm_weights_csr(const sm_plan *plan, sm_precision values, int64_t *nnz_
  * nx*ny*nz*4 int32.  Synchronises the current device. */
 sm_status sm_footprints(const sm_plan *plan, int32_t view, int32_t *boxes_host);
 
+/* ------------------------------------------------------------------------
+ * Reconstruction (Sec. IV, eq. "exp_tikh"): minimise
+ *     F(u) = 1/2 || s W u - p ||^2 + lambda/2 || u ||^2
+ * where s = wscale (the paper divides W by its spectral norm, s = 1/||W||_2,
+ * estimated with 100 power iterations).  All three routines are
+ * stream-ordered on hip_stream, never allocate and never synchronise: every
+ * scalar of the iteration (step sizes, norms) stays in device memory, dot
+ * products are accumulated in FP64 in a fixed order (results are
+ * deterministic), and vectors are in the plan's precision.  They run a fixed
+ * number of iterations; a caller wanting the paper's stopping rule reads the
+ * recorded gradient norms.  ws must hold sm_solver_workspace_size() bytes and
+ * must not be shared with concurrent calls.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    SM_SOLVER_CGLS = 0,  /* sm_cgls */
+    SM_SOLVER_NAG = 1,   /* sm_nag */
+    SM_SOLVER_POWER = 2  /* sm_power_norm (batch must be 1) */
+} sm_solver;
+
+/* Device workspace bytes for one call of the given solver with `batch`
+ * independent right-hand sides (the projector workspace included). */
+sm_status sm_solver_workspace_size(const sm_plan *plan, sm_solver solver, int32_t batch,
+                                   int64_t *bytes);
+
+/* Spectral norm ||W||_2 by power iteration on W^T W (Sec. IV): v = v0/|v0|;
+ * repeat iters times { u = W v; sigma2 = |u|^2; w = W^T u; v = w/|w| };
+ * *norm_dev = sqrt(sigma2) of the last iteration (a Rayleigh quotient, so it
+ * approaches the norm from below).  v0: device volume [nz][ny][nx] (the
+ * random start; the caller draws it), not modified.  norm_dev: device
+ * pointer to one double.  iters >= 1. */
+sm_status sm_power_norm(const sm_plan *plan, const void *v0, int32_t iters, double *norm_dev,
+                        void *ws, int64_t ws_bytes, void *hip_stream);
+
+/* CGLS (conjugate gradients on the normal equations (s^2 W^T W + lambda I)
+ * u = s W^T p) for `batch` independent problems.  y: device sinograms
+ * [batch][n_p][det_nz][det_ny]; x: device volumes [batch][nz][ny][nx], the
+ * start on entry and the iterate after `iters` steps on return.  hist_dev:
+ * NULL, or device doubles [iters + 1][batch] receiving the squared norm of
+ * the normal-equation residual (= |grad F|^2) before each step and after the
+ * last.  lambda >= 0, wscale > 0, iters >= 0. */
+sm_status sm_cgls(const sm_plan *plan, const void *y, void *x, int32_t batch, int32_t iters,
+                  double lambda, double wscale, double *hist_dev, void *ws, int64_t ws_bytes,
+                  void *hip_stream);
+
+/* Nesterov's accelerated gradient (Sec. IV) with the FISTA momentum
+ * t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2 and step 1/L, L = wscale^2 norm^2 +
+ * lambda, where norm is read from device memory (norm_dev, e.g. written by
+ * sm_power_norm).  x: start on entry, u_iters on return.  hist_dev: NULL or
+ * device doubles [iters][batch] receiving |grad F(z_k)|^2 at each
+ * extrapolated point.  lambda >= 0, wscale > 0, iters >= 0. */
+sm_status sm_nag(const sm_plan *plan, const void *y, void *x, int32_t batch, int32_t iters,
+                 double lambda, double wscale, const double *norm_dev, double *hist_dev,
+                 void *ws, int64_t ws_bytes, void *hip_stream);
+
 /* Per-kernel timing, for measurement only (not part of the method).  While
  * timing is enabled on a plan, sm_forward and sm_back record a pair of HIP
  * events on their stream around every dispatch of the kernels below and add

@@ -18,8 +18,11 @@ SM_FP32, SM_FP64 = 0, 1
 
 EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_workspace_size",
             "sm_forward", "sm_back",
-            "sm_weights_csr", "sm_footprints", "sm_timing_enable", "sm_timing_read",
+            "sm_weights_csr", "sm_footprints", "sm_solver_workspace_size", "sm_power_norm",
+            "sm_cgls", "sm_nag", "sm_timing_enable", "sm_timing_read",
             "sm_status_str", "sm_last_error")
+
+SM_SOLVER_CGLS, SM_SOLVER_NAG, SM_SOLVER_POWER = range(3)
 
 # sm_kernel ids (timing)
 KERNELS = ("records", "forward", "adjoint", "prefix", "transpose")
@@ -82,6 +85,17 @@ def lib():
         L.sm_weights_csr.argtypes = [vp, C.c_int, i64p, i64p, i32p, vp]
         L.sm_footprints.restype = C.c_int
         L.sm_footprints.argtypes = [vp, C.c_int32, i32p]
+        dp = C.POINTER(C.c_double)
+        L.sm_solver_workspace_size.restype = C.c_int
+        L.sm_solver_workspace_size.argtypes = [vp, C.c_int, C.c_int32, i64p]
+        L.sm_power_norm.restype = C.c_int
+        L.sm_power_norm.argtypes = [vp, vp, C.c_int32, vp, vp, C.c_int64, vp]
+        L.sm_cgls.restype = C.c_int
+        L.sm_cgls.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, vp, vp,
+                              C.c_int64, vp]
+        L.sm_nag.restype = C.c_int
+        L.sm_nag.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, vp, vp, vp,
+                             C.c_int64, vp]
         L.sm_timing_enable.restype = C.c_int
         L.sm_timing_enable.argtypes = [vp, C.c_int32]
         L.sm_timing_read.restype = C.c_int

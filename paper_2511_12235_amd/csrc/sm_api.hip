@@ -5,38 +5,14 @@
 #include <stdio.h>
 #include <string.h>
 
-#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
-#include "../../include/sm.h"
-#include "sm_internal.h"
+#include "sm_plan.h"
 
 using smk::DevGeom;
 using smk::LaunchCfg;
-
-// Event-pair timing of individual dispatches (sm_timing_enable).
-struct SmTiming {
-    std::mutex mu;
-    bool on = false;
-    std::vector<hipEvent_t> ev;  // pairs: 2 q, 2 q + 1
-    std::vector<int> kernel;     // kernel id of pair q
-    int used = 0;
-    bool overflow = false;
-};
-
-struct sm_plan {
-    int device;
-    sm_precision prec;
-    DevGeom G;
-    LaunchCfg L;
-    smk::RecLayout RL;  // workspace layout of the strip records (3D)
-    double2 *d_trig;
-    double *d_tau;
-    int64_t n_vox, n_rays;
-    SmTiming *tm;
-};
 
 // Views per record chunk: keep the records of one chunk near 1 GiB.
 static const int64_t kRecordBudget = (int64_t)1 << 30;
@@ -128,6 +104,21 @@ __global__ void tile_span_kernel(DevGeom G, int tw, int th, int *out)
 }
 
 }  // namespace
+
+namespace smk {
+sm_status set_error(sm_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+sm_status check_plan_device(const sm_plan *p) { return check_device(p); }
+}  // namespace smk
 
 extern "C" {
 

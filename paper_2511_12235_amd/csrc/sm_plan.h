@@ -1,0 +1,38 @@
+// sm_plan.h -- the plan object behind the opaque sm_plan handle, shared by
+// the API and solver translation units (host side only).
+#pragma once
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/sm.h"
+#include "sm_internal.h"
+
+// Event-pair timing of individual dispatches (sm_timing_enable).
+struct SmTiming {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // pairs: 2 q, 2 q + 1
+    std::vector<int> kernel;     // kernel id of pair q
+    int used = 0;
+    bool overflow = false;
+};
+
+struct sm_plan {
+    int device;
+    sm_precision prec;
+    smk::DevGeom G;
+    smk::LaunchCfg L;
+    smk::RecLayout RL;  // workspace layout of the strip records (3D)
+    double2 *d_trig;
+    double *d_tau;
+    int64_t n_vox, n_rays;
+    SmTiming *tm;
+};
+
+namespace smk {
+// Record an error message for sm_last_error() and return the status.
+sm_status set_error(sm_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+// SM_OK when the plan's device is current.
+sm_status check_plan_device(const sm_plan *p);
+}  // namespace smk

@@ -126,6 +126,69 @@ class SystemMatrix:
 
     __matmul__ = forward
 
+    # ---------------------------------------------------------------- solvers
+    def solver_workspace(self, solver: int, batch: int = 1) -> torch.Tensor:
+        n = C.c_int64()
+        _lib.check(_lib.lib().sm_solver_workspace_size(self._plan, int(solver), int(batch), C.byref(n)),
+                   "sm_solver_workspace_size")
+        return torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+
+    def power_norm(self, v0: torch.Tensor, iters: int = 100, out: torch.Tensor | None = None,
+                   ws: torch.Tensor | None = None) -> torch.Tensor:
+        """||W||_2 by power iteration from the start volume v0 (sm_power_norm);
+        returns a one-element float64 device tensor (no synchronisation)."""
+        if self._check(v0, self.vol_shape, "v0") != 1 or v0.dim() != 3:
+            raise ValueError("v0 must be one volume")
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.device)
+        if ws is None:
+            ws = self.solver_workspace(_lib.SM_SOLVER_POWER, 1)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().sm_power_norm(self._plan, v0.data_ptr(), int(iters), out.data_ptr(),
+                                            ws.data_ptr(), ws.numel(), st), "sm_power_norm")
+        return out
+
+    def _solve_args(self, y, x0, iters, hist_rows):
+        B = self._check(y, self.sino_shape, "y")
+        shape = ((B,) if y.dim() == 4 else ()) + self.vol_shape
+        if x0 is None:
+            x = torch.zeros(shape, dtype=self.dtype, device=self.device)
+        else:
+            if self._check(x0, self.vol_shape, "x0") != B:
+                raise ValueError("x0 batch does not match y")
+            x = x0.clone()
+        hist = torch.empty((hist_rows(iters), B), dtype=torch.float64, device=self.device)
+        return B, x, hist
+
+    def cgls(self, y: torch.Tensor, iters: int, lam: float = 0.0, wscale: float = 1.0,
+             x0: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+        """CGLS for 1/2 |s W x - y|^2 + lam/2 |x|^2 (sm_cgls).  Returns
+        (x, hist) with hist[k] = |grad F(x_k)|^2, k = 0..iters."""
+        B, x, hist = self._solve_args(y, x0, iters, lambda n: n + 1)
+        if ws is None:
+            ws = self.solver_workspace(_lib.SM_SOLVER_CGLS, B)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().sm_cgls(self._plan, y.data_ptr(), x.data_ptr(), B, int(iters), float(lam),
+                                      float(wscale), hist.data_ptr(), ws.data_ptr(), ws.numel(), st),
+                   "sm_cgls")
+        return x, hist
+
+    def nag(self, y: torch.Tensor, iters: int, norm: torch.Tensor, lam: float = 0.0,
+            wscale: float = 1.0, x0: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+        """Nesterov / FISTA for the same objective with step 1/(s^2 norm^2 + lam)
+        (sm_nag); norm is a one-element float64 device tensor such as
+        power_norm() returns.  Returns (x, hist), hist[k] = |grad F(z_k)|^2."""
+        B, x, hist = self._solve_args(y, x0, iters, lambda n: max(n, 1))
+        if not (isinstance(norm, torch.Tensor) and norm.dtype == torch.float64 and norm.device == self.device):
+            raise TypeError("norm must be a float64 tensor on the plan's device")
+        if ws is None:
+            ws = self.solver_workspace(_lib.SM_SOLVER_NAG, B)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().sm_nag(self._plan, y.data_ptr(), x.data_ptr(), B, int(iters), float(lam),
+                                     float(wscale), norm.data_ptr(), hist.data_ptr(), ws.data_ptr(),
+                                     ws.numel(), st), "sm_nag")
+        return x, hist[:iters]
+
     # ----------------------------------------------------------------- timing
     def timing(self, enable: bool = True):
         """Switch per-kernel event timing on or off (sm_timing_enable)."""

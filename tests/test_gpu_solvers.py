@@ -1,0 +1,129 @@
+"""Solvers of the HIP library (sm_power_norm, sm_cgls, sm_nag) against the
+FP64 reference solvers run on the oracle's system matrix.
+
+Inputs (start vectors, data) come from the seeded generators only.  FP64
+plans must follow the reference iterates to 1e-9 relative L2 over 10
+iterations.  FP32 plans must follow them to 1e-4 while the iteration is
+above FP32's floor: once the normal-equation residual |g_k|^2 falls to about
+1e-5 |g_0|^2, rounding in g = s W^T r - lambda x (a difference of O(|W^T p|)
+terms) dominates it and CG's recurrences depart from exact arithmetic.  A
+NumPy replay of the same recurrence in FP32 departs identically (about 1e-2
+on the 2D problem after 10 steps), so FP32 CGLS is compared over 5 steps.
+Batched solves equal single solves bitwise."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from oracle import solvers as S
+from paper_2511_12235_amd import _lib
+from paper_2511_12235_amd import workloads as wl
+from paper_2511_12235_amd.projector import SystemMatrix
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {"fp64": 1e-9, "fp32": 1e-4}
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _t(a, prec):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, torch.float64 if prec == "fp64" else torch.float32)
+
+
+GEOMS = {
+    "fan_small": wl.make_geometry(2, (20, 17), (1.0, 1.1), 30, 60.0, 50.0, (36,), (1.3,)),
+    "cone_small": wl.scaled(wl.c2_cone128(), (18, 16, 14), (24, 20), 16),
+}
+_W = {}
+
+
+def _matrix(name):
+    if name not in _W:
+        _W[name] = O.matrix(GEOMS[name])
+    return _W[name]
+
+
+def _problem(name):
+    g = GEOMS[name]
+    W = _matrix(name)
+    x_true = wl.ellipse_phantom(g, 4, seed=12).ravel()
+    y = W @ x_true + 1e-4 * wl.random_unit(g.n_rays, 13).ravel()
+    return g, W, y.reshape(g.sino_shape)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_power_norm(name, prec):
+    print("[case] power", name, prec, flush=True)
+    g = GEOMS[name]
+    v0 = wl.uniform(g.vol_shape, 11)
+    ref = S.power_norm(_matrix(name), v0, 30)
+    A = SystemMatrix(g, prec, device=DEV)
+    got = float(A.power_norm(_t(v0, prec), 30).item())
+    assert abs(got - ref) / ref <= (1e-12 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_cgls(name, prec):
+    print("[case] cgls", name, prec, flush=True)
+    g, W, y = _problem(name)
+    norm = S.power_norm(W, wl.uniform(g.vol_shape, 11), 50)
+    lam, s = 1e-3, 1.0 / norm
+    iters = 10 if prec == "fp64" else 5
+    x_ref, h_ref = S.cgls(W, y, np.zeros(g.n_vox), iters, lam=lam, s=s)
+    A = SystemMatrix(g, prec, device=DEV)
+    x, h = A.cgls(_t(y, prec), iters, lam=lam, wscale=s)
+    assert _rel(x.cpu().numpy(), x_ref) <= TOL[prec]
+    assert _rel(h.cpu().numpy()[:, 0], h_ref) <= (1e-9 if prec == "fp64" else 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_nag(name, prec):
+    print("[case] nag", name, prec, flush=True)
+    g, W, y = _problem(name)
+    v0 = wl.uniform(g.vol_shape, 11)
+    norm = S.power_norm(W, v0, 50)
+    lam, s = 1e-3, 1.0 / norm
+    x_ref, h_ref = S.nag(W, y, np.zeros(g.n_vox), 10, norm, lam=lam, s=s)
+    A = SystemMatrix(g, prec, device=DEV)
+    nd = torch.tensor([norm], dtype=torch.float64, device=DEV)
+    x, h = A.nag(_t(y, prec), 10, nd, lam=lam, wscale=s)
+    assert _rel(x.cpu().numpy(), x_ref) <= TOL[prec]
+    assert _rel(h.cpu().numpy()[:, 0], h_ref) <= (1e-9 if prec == "fp64" else 1e-3)
+
+
+def test_batched_solves_equal_single_bitwise():
+    print("[case] batched solves", flush=True)
+    g = GEOMS["cone_small"]
+    A = SystemMatrix(g, "fp32", device=DEV)
+    ys = torch.stack([_t(wl.uniform(g.sino_shape, 20 + i), "fp32") for i in range(3)])
+    xb, hb = A.cgls(ys, 6, lam=1e-2, wscale=0.05)
+    nd = torch.tensor([3.0], dtype=torch.float64, device=DEV)
+    zb, gb = A.nag(ys, 5, nd, lam=1e-2, wscale=0.05)
+    for i in range(3):
+        x1, h1 = A.cgls(ys[i].contiguous(), 6, lam=1e-2, wscale=0.05)
+        assert torch.equal(xb[i], x1) and torch.equal(hb[:, i], h1[:, 0])
+        z1, g1 = A.nag(ys[i].contiguous(), 5, nd, lam=1e-2, wscale=0.05)
+        assert torch.equal(zb[i], z1) and torch.equal(gb[:, i], g1[:, 0])
+
+
+def test_solver_argument_errors():
+    g = GEOMS["fan_small"]
+    A = SystemMatrix(g, "fp32", device=DEV)
+    y = _t(wl.uniform(g.sino_shape, 1), "fp32")
+    with pytest.raises(_lib.SmError):
+        A.cgls(y, -1)
+    with pytest.raises(_lib.SmError):
+        A.cgls(y, 2, lam=-1.0)
+    with pytest.raises(_lib.SmError):
+        A.solver_workspace(_lib.SM_SOLVER_POWER, 2)
+    ws = A.solver_workspace(_lib.SM_SOLVER_CGLS, 1)
+    with pytest.raises(_lib.SmError):
+        A.cgls(y, 2, ws=ws[: ws.numel() // 2])
