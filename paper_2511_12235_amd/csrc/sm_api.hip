@@ -256,6 +256,15 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
     const int tw[5] = {4, 4, 2, 2, 1}, th[5] = {4, 2, 2, 1, 1};
     for (int i = 0; i < 4; ++i) L.back_pcols[i] = 1;
     L.rspan = 1;
+    // Adjoint view runs: enough workgroups x waves to fill the device for
+    // small volumes (a function of the geometry only, so results do not
+    // depend on the device).
+    {
+        const int64_t tiles = (int64_t)((G.nx + 3) / 4) * ((G.ny + 3) / 4);
+        const int64_t waves = tiles * (L.back_threads / 64);
+        int64_t gr = (8192 + waves - 1) / (waves > 0 ? waves : 1);
+        L.back_groups = (int)(gr < 1 ? 1 : (gr > 16 ? 16 : gr));
+    }
     p->RL = smk::RecLayout{};
     if (e == hipSuccess && G.dim == 3) {
         int *d_span = nullptr;
@@ -324,7 +333,10 @@ static int64_t workspace_bytes(const sm_plan *p, int64_t batch)
 {
     if (p->G.dim != 3) return 0;
     const int64_t npix = (int64_t)p->G.nx * p->G.ny;
-    return p->RL.data_off + npix * batch * (int64_t)(p->G.nz + 1) * (int64_t)sizeof(double);
+    const int64_t es = p->prec == SM_FP64 ? 8 : 4;
+    const int64_t fwd = npix * batch * (int64_t)(p->G.nz + 1) * (int64_t)sizeof(double);
+    const int64_t adj = (int64_t)p->L.back_groups * npix * batch * p->G.nz * es;
+    return p->RL.data_off + (fwd > adj ? fwd : adj);
 }
 
 sm_status sm_workspace_size(const sm_plan *p, int32_t batch, int64_t *bytes)
@@ -413,7 +425,8 @@ sm_status sm_back(const sm_plan *p, const void *y, void *x, int32_t batch, void 
         }
         if (e == hipSuccess) {
             q = tm_begin(p, SM_KERNEL_TRANSPOSE, st);
-            e = smk::launch_from_columns(xt, x, f64 ? 8 : 4, batch, p->G.nz, p->G.ny, p->G.nx, st);
+            e = smk::launch_from_columns(xt, x, f64 ? 8 : 4, batch, p->G.nz, p->G.ny, p->G.nx,
+                                         p->L.back_groups, st);
             tm_end(p, q, st);
         }
     }

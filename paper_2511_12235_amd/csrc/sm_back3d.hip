@@ -2,7 +2,9 @@
 //
 // Voxel-stationary gather, no atomics: a workgroup owns a TX x TY tile of
 // pixels and every voxel above them (one lane per z index) and keeps the
-// tile's sums in registers while it loops over the views of a chunk.  Per
+// tile's sums in registers while it loops over a run of views of a chunk
+// (small volumes split the chunk's views into several runs, each with its
+// own partial volume, so that the grid fills the device).  Per
 // view it stages in LDS the detector columns the tile can meet (all rows, with
 // a zero row above and below) and the strip records of the tile's pixels
 // (built by sm_rec.hip).  For every (pixel, column) record lane iz then adds
@@ -25,7 +27,7 @@ __global__ void __launch_bounds__(1024)
 back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict__ recs,
               const int *__restrict__ sj0, const int *__restrict__ soff,
               const int2 *__restrict__ pixk, const T *__restrict__ y, T *__restrict__ xt, int B,
-              int b0, int pcols, int rspan, int first)
+              int b0, int pcols, int rspan, int first, int groups)
 {
     constexpr int TP = TX * TY;
     constexpr int RCH = (int)(sizeof(Rec<T>) / 16);  // 16-byte chunks per record
@@ -52,9 +54,15 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
         pinv[p] = t != 0.0 ? T(1) / T(t) : T(0);
     }
 
-    const int ntx = (G.nx + TX - 1) / TX;
+    const int ntx = (G.nx + TX - 1) / TX, nty = (G.ny + TY - 1) / TY;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int tyi = lb / ntx, txi = lb - tyi * ntx;
+    // view group: the chunk's views are split into `groups` contiguous runs,
+    // each summed into its own partial volume
+    const int grp = lb / (ntx * nty);
+    const int tile = lb - grp * ntx * nty;
+    const int vbeg = (int)((int64_t)nvc * grp / groups), vend = (int)((int64_t)nvc * (grp + 1) / groups);
+    xt += (size_t)grp * G.nx * G.ny * B * G.nz;
+    const int tyi = tile / ntx, txi = tile - tyi * ntx;
     const int ix0 = txi * TX, iy0 = tyi * TY;
     const int npix = G.nx * G.ny;
 
@@ -71,7 +79,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) acc[p][b] = T(0);
 
-    for (int vl = 0; vl < nvc; ++vl) {
+    for (int vl = vbeg; vl < vend; ++vl) {
         const int view = v0 + vl;
         const double2 cs = G.trig[view];
         const StripAxis ax = strip_axis(G, cs.x, cs.y);
@@ -191,9 +199,10 @@ static hipError_t launch_back3d_t(const DevGeom &G, const LaunchCfg &L, const Re
     const size_t lds = back3d_lds<T, NBAT, TX, TY>(G, L, slot);
     if (lds > (size_t)L.lds_budget) return hipErrorInvalidValue;
     const int ntx = (G.nx + TX - 1) / TX, nty = (G.ny + TY - 1) / TY;
-    hipLaunchKernelGGL((back3d_kernel<T, NBAT, TX, TY>), dim3(ntx * nty), dim3(L.back_threads), lds,
-                       st, G, RL, v0, nvc, (const Rec<T> *)RP.recs, RP.sj0, RP.soff, RP.pixk, y, xt,
-                       B, b0, L.back_pcols[slot], L.rspan, first ? 1 : 0);
+    hipLaunchKernelGGL((back3d_kernel<T, NBAT, TX, TY>), dim3(ntx * nty * L.back_groups),
+                       dim3(L.back_threads), lds, st, G, RL, v0, nvc, (const Rec<T> *)RP.recs, RP.sj0,
+                       RP.soff, RP.pixk, y, xt, B, b0, L.back_pcols[slot], L.rspan, first ? 1 : 0,
+                       L.back_groups);
     return hipGetLastError();
 }
 

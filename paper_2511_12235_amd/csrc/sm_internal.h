@@ -15,6 +15,7 @@ struct LaunchCfg {
     int back_threads;  // 64 * ceil(nz / 64)
     int back_pcols[4]; // detector columns an adjoint tile can meet (max over views)
     int rspan;         // detector columns a single pixel can meet (max over views)
+    int back_groups;   // view runs per chunk in the adjoint (partial volumes)
     int lds_budget;    // dynamic LDS bytes a workgroup may use
 };
 
@@ -75,9 +76,9 @@ hipError_t launch_strip_count(const DevGeom &G, int *max_count, hipStream_t st);
 // x[B][nz][ny][nx] -> FP64 prefix sums along z, P[ny*nx][B][nz + 1]
 hipError_t launch_prefix_columns(const void *x, double *P, bool fp64, int B, int nz, int ny, int nx,
                                  hipStream_t st);
-// xt[ny*nx][B][nz] -> x[B][nz][ny][nx]
+// sum over g of xt[g][ny*nx][B][nz] -> x[B][nz][ny][nx] (partials added in order)
 hipError_t launch_from_columns(const void *xt, void *x, int elem, int B, int nz, int ny, int nx,
-                               hipStream_t st);
+                               int groups, hipStream_t st);
 
 hipError_t launch_fwd3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,
                         int v0, int nvc, void *ws, const double *P, void *y, int B, hipStream_t st);

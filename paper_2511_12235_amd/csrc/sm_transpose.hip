@@ -3,7 +3,8 @@
 //   forward input : FP64 prefix sums along z, P[ny*nx][B][nz + 1] with
 //                   P[.][.][0] = 0 and P[.][.][i+1] = x_0 + ... + x_i, so any
 //                   run of voxels of a column sums with one subtraction;
-//   adjoint output: xt[ny*nx][B][nz] (z contiguous), transposed back here.
+//   adjoint output: xt[g][ny*nx][B][nz] (z contiguous), one partial volume per
+//                   view run g, summed in order and transposed back here.
 // Both go through LDS so global reads and writes stay coalesced.
 #include "sm_internal.h"
 
@@ -48,7 +49,7 @@ __global__ void __launch_bounds__(256) prefix_kernel(const T *__restrict__ x, do
 
 template <typename T>
 __global__ void __launch_bounds__(256) from_columns_kernel(const T *__restrict__ xt, T *__restrict__ x,
-                                                            int B, int nz, int ny, int nx)
+                                                            int B, int nz, int ny, int nx, int groups)
 {
     __shared__ T tile[32][33];
     const int s = blockIdx.z;
@@ -57,7 +58,13 @@ __global__ void __launch_bounds__(256) from_columns_kernel(const T *__restrict__
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int j = ty; j < 32; j += 8) {
         const int ix = ix0 + j, iz = iz0 + tx;
-        if (iz < nz && ix < nx) tile[j][tx] = xt[(((size_t)iy * nx + ix) * B + b) * nz + iz];
+        if (iz < nz && ix < nx) {
+            const size_t o = (((size_t)iy * nx + ix) * B + b) * nz + iz;
+            const size_t gs = (size_t)nx * ny * B * nz;
+            T v = xt[o];
+            for (int g = 1; g < groups; ++g) v += xt[(size_t)g * gs + o];
+            tile[j][tx] = v;
+        }
     }
     __syncthreads();
     for (int j = ty; j < 32; j += 8) {
@@ -85,15 +92,15 @@ hipError_t launch_prefix_columns(const void *x, double *P, bool fp64, int B, int
 }
 
 hipError_t launch_from_columns(const void *xt, void *x, int elem, int B, int nz, int ny, int nx,
-                               hipStream_t st)
+                               int groups, hipStream_t st)
 {
     dim3 grid((nx + 31) / 32, (nz + 31) / 32, B * ny);
     if (elem == 8)
         hipLaunchKernelGGL(from_columns_kernel<double>, grid, dim3(256), 0, st, (const double *)xt,
-                           (double *)x, B, nz, ny, nx);
+                           (double *)x, B, nz, ny, nx, groups);
     else
         hipLaunchKernelGGL(from_columns_kernel<float>, grid, dim3(256), 0, st, (const float *)xt,
-                           (float *)x, B, nz, ny, nx);
+                           (float *)x, B, nz, ny, nx, groups);
     return hipGetLastError();
 }
 
