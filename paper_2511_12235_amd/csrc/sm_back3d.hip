@@ -71,7 +71,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
     const double za = G.z0 + (double)iz * G.c;
     const double zb = G.z0 + (double)(iz + 1) * G.c;
     const T cT = T(G.c);
-    const T tDdv = T(G.D / G.dv), v0dv = T(G.v0 / G.dv);
+    const T v0dv = T(G.v0 / G.dv);
 
     T acc[TP][NBAT];
 #pragma unroll
@@ -83,18 +83,13 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
         const int view = v0 + vl;
         const double2 cs = G.trig[view];
         const StripAxis ax = strip_axis(G, cs.x, cs.y);
-        // detector columns of the tile's pixels (from the record pass)
-        int kk0[TP], kk1[TP];
+        // detector columns the tile's pixels meet (from the record pass)
         int kmin = 1 << 30, kmax = -1;
 #pragma unroll
         for (int p = 0; p < TP; ++p) {
             const int ix = ix0 + p % TX, iy = iy0 + p / TX;
-            kk0[p] = 0;
-            kk1[p] = -1;
             if (ix < G.nx && iy < G.ny) {
                 const int2 q = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
-                kk0[p] = q.x;
-                kk1[p] = min(q.y, q.x + rspan - 1);  // rspan bounds every pixel's span
                 if (q.y >= q.x) {
                     kmin = min(kmin, q.x);
                     kmax = max(kmax, q.y);
@@ -123,45 +118,66 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
                 }
             }
         }
-        // --- stage the strip records of the tile's pixels in slot (p, k - kk0[p])
+        // --- stage the strip records of the tile's pixels in slot (p, k - k0(p));
+        // a slot without a record gets n = 0
         for (int q = tid; q < TP * rspan * RCH; q += nthr) {
             const int p = q / (rspan * RCH);
             const int rem = q - p * rspan * RCH;
             const int kk = rem / RCH, ch = rem - kk * RCH;
             const int ix = ix0 + p % TX, iy = iy0 + p / TX;
-            if (ix >= G.nx || iy >= G.ny) continue;
-            const int2 kr = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
-            const int k = kr.x + kk;
-            if (k > kr.y || k < kmin || k > kmax) continue;
-            const int64_t strip = (int64_t)vl * G.nu + k;
-            const int pos = strip_position(ax.major_x, ix, iy, sj0 + strip * RL.n_major_max,
-                                           soff + strip * (RL.n_major_max + 1));
-            if (pos < 0) continue;
-            const uint4 *src = reinterpret_cast<const uint4 *>(recs + strip * RL.cap + pos);
             uint4 *dst = reinterpret_cast<uint4 *>(rtab + p * rspan + kk);
-            dst[ch] = src[ch];
+            int pos = -1;
+            int64_t strip = 0;
+            if (ix < G.nx && iy < G.ny) {
+                const int2 kr = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
+                const int k = kr.x + kk;
+                if (k <= kr.y && k >= kmin && k <= kmax) {
+                    strip = (int64_t)vl * G.nu + k;
+                    pos = strip_position(ax.major_x, ix, iy, sj0 + strip * RL.n_major_max,
+                                         soff + strip * (RL.n_major_max + 1));
+                }
+            }
+            if (pos >= 0)
+                dst[ch] = reinterpret_cast<const uint4 *>(recs + strip * RL.cap + pos)[ch];
+            else if (ch == 0)
+                dst[0] = make_uint4(0u, 0u, 0u, 0u);  // lc = 0, n = 0
         }
         __syncthreads();
         if (!active) continue;
-#pragma unroll
+        // Pixels in a runtime loop: the current pixel's sums are acc[0]; the
+        // array rotates by one slot per pixel, so after TP pixels every sum
+        // is back in its own slot (keeps the code small and the sums in
+        // registers).
+#pragma unroll 1
         for (int p = 0; p < TP; ++p) {
             const int ix = ix0 + p % TX, iy = iy0 + p / TX;
-            for (int k = max(kk0[p], kmin); k <= min(kk1[p], kmax); ++k) {
-                const int64_t strip = (int64_t)vl * G.nu + k;
-                const int pos = strip_position(ax.major_x, ix, iy, sj0 + strip * RL.n_major_max,
-                                               soff + strip * (RL.n_major_max + 1));
-                if (pos < 0) continue;
-                const Rec<T> &R = recs[strip * RL.cap + pos];
-                const int n = R.n;
+            int k0 = 0, k1 = -1;
+            if (ix < G.nx && iy < G.ny) {
+                const int2 q = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
+                k0 = q.x;
+                k1 = min(min(q.y, q.x + rspan - 1), kmax);  // rspan bounds every pixel's span
+            }
+            T cur[NBAT];
+#pragma unroll
+            for (int b = 0; b < NBAT; ++b) cur[b] = acc[0][b];
+            for (int k = max(k0, kmin); k <= k1; ++k) {
+                const Rec<T> &R = rtab[p * rspan + (k - k0)];  // LDS copy
+                const int n = __builtin_amdgcn_readfirstlane(R.n);
                 if (n == 0) continue;
-                const StripTab<T> S = strip_tab<T>(R.tab, rtab[p * rspan + (k - kk0[p])].tab);
+                const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
                 const T *Y = patch + (size_t)(k - kmin) * rowstride + 1;  // Y[-1] .. Y[nv]
                 T sum[NBAT];
-                adj_terms<T, NBAT>(S, R.lc, R.tab[n - 1][0], ptau, ptf, pinv, za, zb, tDdv, v0dv,
-                                   nv, cT, Y, (size_t)pcols * rowstride, sum);
+                adj_terms<T, NBAT>(S, R.lc, R.lbo, R.kLo, R.kHi, ptau, ptf, pinv, za, zb, v0dv, nv,
+                                   cT, Y, (size_t)pcols * rowstride, sum);
 #pragma unroll
-                for (int b = 0; b < NBAT; ++b) acc[p][b] += sum[b];
+                for (int b = 0; b < NBAT; ++b) cur[b] += sum[b];
             }
+#pragma unroll
+            for (int i = 0; i + 1 < TP; ++i)
+#pragma unroll
+                for (int b = 0; b < NBAT; ++b) acc[i][b] = acc[i + 1][b];
+#pragma unroll
+            for (int b = 0; b < NBAT; ++b) acc[TP - 1][b] = cur[b];
         }
     }
 

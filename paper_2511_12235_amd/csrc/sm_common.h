@@ -56,14 +56,18 @@ constexpr int MAXV = 6;  // vertices of a strip polygon (rectangle cut by two li
 // Strip record: pixel `pix` cut by detector column k in one view.
 // tab[i] = (depth l', chord width w, S0, S1) for the breakpoints in ascending
 // depth, S0 = integral of w beyond the depth, S1 = first moment of w beyond
-// the depth about the depth itself.  Area = tab[0][2].
+// the depth about the depth itself.  Area = tab[0][2].  The header also holds
+// the area-weighted mean depth relative to lc and the row-plane index scales
+// D / (L dv) at the nearest and farthest depth L (see plane_split), all
+// computed in FP64.  128 bytes for T = float, 240 for T = double.
 template <typename T>
 struct alignas(16) Rec {
     double lc;  // depth of the pixel centre
     int n;      // number of breakpoints, 0 when the polygon is empty
     int k;      // detector column
     int pix;    // pixel index iy * nx + ix
-    int pad;
+    T lbo;      // area-weighted mean depth minus lc
+    T kLo, kHi; // D / (Llo dv), D / (Lhi dv)
     T tab[MAXV][4];
 };
 
@@ -149,6 +153,9 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
 
     R.lc = lc;
     R.k = k;
+    R.lbo = T(0);
+    R.kLo = T(0);
+    R.kHi = T(0);
     if (m < 3) {
         R.n = 0;
         return;
@@ -217,6 +224,12 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
         }
     }
     R.n = S0[0] > 0.0 ? m : 0;
+    if (S0[0] > 0.0) {
+        const double Ddv = G.D / G.dv;
+        R.lbo = T(bd[0] + S1[0] / S0[0]);
+        R.kLo = T(Ddv / (lc + bd[0]));
+        R.kHi = T(Ddv / (lc + bd[m - 1]));
+    }
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
         R.tab[i][0] = T(i < m ? bd[i] : bd[m - 1]);
@@ -354,7 +367,6 @@ __host__ __device__ inline StripTab<T> strip_tab(const T (*tab)[4], const T (*ro
 template <typename T>
 __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
 {
-    if (tau == T(0)) return e > T(0) ? e * S.A : T(0);
     const T lam = -e * inv_tau;
     const int j = (lam >= S.b1 ? 1 : 0) + (lam >= S.b2 ? 1 : 0) + (lam >= S.b3 ? 1 : 0) +
                   (lam >= S.b4 ? 1 : 0);
@@ -369,8 +381,10 @@ __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
     T psi = h * h * (wl * T(1.0 / 6.0) + w1 * T(1.0 / 3.0)) + s1 + h * s0;
     const T below = S.d0 - lam;
     psi += (below > T(0) ? below : T(0)) * S.A;
-    if (tau > T(0)) return tau * psi;
-    return (-tau) * (psi - S.S1 + (lam - S.d0) * S.A);
+    const T kp = tau * psi;                                  // tau > 0
+    const T kn = (-tau) * (psi - S.S1 + (lam - S.d0) * S.A);  // tau < 0
+    const T k0 = e > T(0) ? e * S.A : T(0);                   // horizontal plane
+    return tau > T(0) ? kp : (tau < T(0) ? kn : k0);
 }
 
 // Heights of plane tau over the strip [Llo, Lhi] (depths).
@@ -432,14 +446,12 @@ __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, 
 // Y[b * ystride + q] holds y[q] of batch element b for q in [-1, nv];
 // ptau / ptf / pinv are the plane slopes in FP64, in T and their inverses.
 template <typename T, int NBAT>
-__host__ __device__ inline void adj_terms(const StripTab<T> &S, double lc, T dn,
+__host__ __device__ inline void adj_terms(const StripTab<T> &S, double lc, T lbo, T kLo, T kHi,
                                           const double *ptau, const T *ptf, const T *pinv,
-                                          double za, double zb, T tDdv, T v0dv, int nv, T cT,
+                                          double za, double zb, T v0dv, int nv, T cT,
                                           const T *Y, size_t ystride, T (&sum)[NBAT])
 {
-    const T kLo = tDdv / T(lc + (double)S.d0);
-    const T kHi = tDdv / T(lc + (double)dn);
-    const double lbar = lc + (double)(S.d0 + S.S1 / S.A);  // area-weighted mean depth
+    const double lbar = lc + (double)lbo;  // area-weighted mean depth
     int pha, paa, phb, pab;
     plane_split<T>(T(za), kLo, kHi, v0dv, nv, pha, paa);
     plane_split<T>(T(zb), kLo, kHi, v0dv, nv, phb, pab);

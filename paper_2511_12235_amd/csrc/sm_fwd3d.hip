@@ -80,7 +80,7 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
                 const StripTab<T> S = strip_tab<T>(R.tab, rbuf[e].tab);
                 const double lc = R.lc;
                 const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
-                const double lbar = lc + (double)(S.d0 + S.S1 / S.A);
+                const double lbar = lc + (double)R.lbo;
                 const double *Pc[NBAT];
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;
@@ -109,7 +109,7 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
                 const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
                 const double lc = R.lc;
                 const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
-                const double lbar = lc + (double)(S.d0 + S.S1 / S.A);
+                const double lbar = lc + (double)R.lbo;
                 const double *Pc[NBAT];
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;

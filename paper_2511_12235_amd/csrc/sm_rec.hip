@@ -96,7 +96,6 @@ rec_kernel(DevGeom G, RecLayout RL, int v0, Rec<T> *__restrict__ recs, int *__re
                 Rec<T> R;
                 build_record<T>(G, cp, sp, ix, iy, k, R, wsp[tid]);
                 R.pix = iy * G.nx + ix;
-                R.pad = 0;
                 out[slot] = R;
                 if (R.n > 0) {
                     atomicMin(&pk[R.pix].x, k);
