@@ -289,6 +289,13 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
         V = V < 1 ? 1 : (V > G.n_p ? G.n_p : V);
         p->RL = smk::make_layout(cap, G.nx > G.ny ? G.nx : G.ny, (int)V, G.nu, G.nx, G.ny, rsz);
         const size_t need = smk::back3d_lds_min(G, L, precision == SM_FP64);
+        if (e == hipSuccess && !smk::fwd3d_fits(L, precision == SM_FP64)) {
+            hipFree(p->d_trig);
+            hipFree(p->d_tau);
+            delete p->tm;
+            delete p;
+            return fail(SM_EUNSUPPORTED, "too many detector rows for the forward's LDS staging");
+        }
         if (e == hipSuccess && need > (size_t)L.lds_budget) {
             hipFree(p->d_trig);
             hipFree(p->d_tau);

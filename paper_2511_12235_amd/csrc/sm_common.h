@@ -396,12 +396,15 @@ __host__ __device__ inline void plane_extent(T tau, T Llo, T Lhi, T &lo, T &hi)
     hi = tau >= T(0) ? b : a;
 }
 
-// G_p of one plane for one strip record; f_out = first voxel not wholly below.
+// The part of G_p of one plane for one strip record that needs no chord
+// table: the linear volume at face f = fa - 1 (the first voxel not wholly
+// below the plane).  Faces fa .. je are straddled (empty when je < fa); their
+// terms come from straddle_term.
 template <typename T, int NBAT>
-__host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, double lc,
-                                        double lbar, T Llo, T Lhi, double tau, T tauf, T invt,
-                                        T inv_c, T z0c, const double *const (&Pc)[NBAT], int &f_out,
-                                        T (&gs)[NBAT])
+__host__ __device__ inline void plane_lin(const DevGeom &G, const StripTab<T> &S, double lbar,
+                                          T Llo, T Lhi, double tau, T tauf, T inv_c, T z0c,
+                                          const double *const (&Pc)[NBAT], int &f_out, int &fa_out,
+                                          int &je_out, T (&gs)[NBAT])
 {
     const int nz = G.nz;
     T lo, hi;
@@ -410,72 +413,115 @@ __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, 
     face_split<T>(lo, hi, inv_c, z0c, nz, fa, fb);
     const int f = fa - 1 < 0 ? 0 : (fa - 1 > nz ? nz : fa - 1);
     f_out = f;
+    fa_out = fa;
+    je_out = fb - 1 < nz ? fb - 1 : nz;
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) gs[b] = T(0);
-    double Pm[NBAT], P0[NBAT];  // P[j - 1], P[j] along the straddle walk
     if (fa >= 1 && fa <= nz) {  // face f wholly below the plane: linear volume
         const T K = S.A * T(tau * lbar - (G.z0 + (double)f * G.c));
 #pragma unroll
-        for (int b = 0; b < NBAT; ++b) {
-            Pm[b] = Pc[b][f];
-            P0[b] = Pc[b][f + 1];
-            gs[b] = K * T(P0[b] - Pm[b]);
-        }
-    } else {
-#pragma unroll
-        for (int b = 0; b < NBAT; ++b) Pm[b] = P0[b] = Pc[b][fa > nz ? nz : 0];
+        for (int b = 0; b < NBAT; ++b) gs[b] = K * T(Pc[b][f + 1] - Pc[b][f]);
     }
-    const int je = fb - 1 < nz ? fb - 1 : nz;
-    for (int j = fa; j <= je; ++j) {  // straddled faces
-        const T e = T(tau * lc - (G.z0 + (double)j * G.c));
-        const T K = K_cut<T>(S, tauf, invt, e);
+}
+
+// Term K_p(z_j) (x_j - x_{j-1}) of a straddled face j (x_{-1} = x_nz = 0).
+template <typename T, int NBAT>
+__host__ __device__ inline void straddle_term(const DevGeom &G, const StripTab<T> &S, double lc,
+                                              double tau, T tauf, T invt, int j,
+                                              const double *const (&Pc)[NBAT], T (&out)[NBAT])
+{
+    const int nz = G.nz;
+    const T K = K_cut<T>(S, tauf, invt, T(tau * lc - (G.z0 + (double)j * G.c)));
 #pragma unroll
-        for (int b = 0; b < NBAT; ++b) {
-            const double Pn = j < nz ? Pc[b][j + 1] : P0[b];
-            const T xj = T(Pn - P0[b]);
-            const T xm = j >= 1 ? T(P0[b] - Pm[b]) : T(0);
-            gs[b] += K * (xj - xm);
-            Pm[b] = P0[b];
-            P0[b] = Pn;
-        }
+    for (int b = 0; b < NBAT; ++b) {
+        const double P0 = Pc[b][j];
+        const T xj = j < nz ? T(Pc[b][j + 1] - P0) : T(0);
+        const T xm = j >= 1 ? T(P0 - Pc[b][j - 1]) : T(0);
+        out[b] = K * (xj - xm);
     }
+}
+
+// G_p of one plane for one strip record; f_out = first voxel not wholly below.
+template <typename T, int NBAT>
+__host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, double lc,
+                                        double lbar, T Llo, T Lhi, double tau, T tauf, T invt,
+                                        T inv_c, T z0c, const double *const (&Pc)[NBAT], int &f_out,
+                                        T (&gs)[NBAT])
+{
+    int fa, je;
+    plane_lin<T, NBAT>(G, S, lbar, Llo, Lhi, tau, tauf, inv_c, z0c, Pc, f_out, fa, je, gs);
+    for (int j = fa; j <= je; ++j) {
+        T t[NBAT];
+        straddle_term<T, NBAT>(G, S, lc, tau, tauf, invt, j, Pc, t);
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) gs[b] += t[b];
+    }
+}
+
+// The part of one strip record's contribution to voxel [za, zb] of its column
+// in the adjoint that needs no chord table: c A y[pab - 1] for the planes
+// wholly above the voxel plus the linear volumes at za of the planes wholly
+// above za that reach below zb.  Planes pha .. paa - 1 straddle za and
+// phb .. pab - 1 straddle zb (adj_straddle gives their terms).
+// Y[b * ystride + q] holds y[q] of batch element b for q in [-1, nv];
+// ptau / ptf / pinv are the plane slopes in FP64, in T and their inverses.
+template <typename T, int NBAT>
+__host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T lbo, T kLo, T kHi,
+                                        const double *ptau, double za, double zb, T v0dv, int nv,
+                                        T cT, const T *Y, size_t ystride, int &pha, int &paa,
+                                        int &phb, int &pab, T (&sum)[NBAT])
+{
+    const double lbar = lc + (double)lbo;  // area-weighted mean depth
+    plane_split<T>(T(za), kLo, kHi, v0dv, nv, pha, paa);
+    plane_split<T>(T(zb), kLo, kHi, v0dv, nv, phb, pab);
+    const T cA = cT * S.A;
+#pragma unroll
+    for (int b = 0; b < NBAT; ++b) sum[b] = cA * Y[b * ystride + pab - 1];
+    for (int q = paa; q < pab; ++q) {
+        const T K = S.A * T(ptau[q] * lbar - za);
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) sum[b] += K * (Y[b * ystride + q - 1] - Y[b * ystride + q]);
+    }
+}
+
+// Straddle term t of a voxel (t < na: plane pha + t at za, added; else plane
+// phb + t - na at zb, subtracted): the plane q, the face height e and the
+// signed row differences; the term is K_cut(e) * dY.
+template <typename T, int NBAT>
+__host__ __device__ inline int adj_straddle(int t, int na, int pha, int phb, const double *ptau,
+                                            double lc, double za, double zb, const T *Y,
+                                            size_t ystride, T &e, T (&dY)[NBAT])
+{
+    const bool top = t >= na;
+    const int q = top ? phb + (t - na) : pha + t;
+    e = T(ptau[q] * lc - (top ? zb : za));
+#pragma unroll
+    for (int b = 0; b < NBAT; ++b) {
+        const T d = Y[b * ystride + q - 1] - Y[b * ystride + q];
+        dY[b] = top ? -d : d;
+    }
+    return q;
 }
 
 // One strip record's contribution to voxel [za, zb] of its column in the
 // adjoint: sum_q (K_q(za) - K_q(zb)) (y[q-1] - y[q]) with y[-1] = y[nv] = 0.
-// Y[b * ystride + q] holds y[q] of batch element b for q in [-1, nv];
-// ptau / ptf / pinv are the plane slopes in FP64, in T and their inverses.
 template <typename T, int NBAT>
 __host__ __device__ inline void adj_terms(const StripTab<T> &S, double lc, T lbo, T kLo, T kHi,
                                           const double *ptau, const T *ptf, const T *pinv,
                                           double za, double zb, T v0dv, int nv, T cT,
                                           const T *Y, size_t ystride, T (&sum)[NBAT])
 {
-    const double lbar = lc + (double)lbo;  // area-weighted mean depth
     int pha, paa, phb, pab;
-    plane_split<T>(T(za), kLo, kHi, v0dv, nv, pha, paa);
-    plane_split<T>(T(zb), kLo, kHi, v0dv, nv, phb, pab);
-    // planes from pab up lie wholly above the voxel: c A each, telescoped
-    const T cA = cT * S.A;
-#pragma unroll
-    for (int b = 0; b < NBAT; ++b) sum[b] = cA * Y[b * ystride + pab - 1];
-    // planes wholly above za that reach below zb: linear volume at za
-    for (int q = paa; q < pab; ++q) {
-        const T K = S.A * T(ptau[q] * lbar - za);
-#pragma unroll
-        for (int b = 0; b < NBAT; ++b) sum[b] += K * (Y[b * ystride + q - 1] - Y[b * ystride + q]);
-    }
-    // planes straddling za (+K) or zb (-K), one merged loop
+    adj_lin<T, NBAT>(S, lc, lbo, kLo, kHi, ptau, za, zb, v0dv, nv, cT, Y, ystride, pha, paa, phb,
+                     pab, sum);
     const int na = paa > pha ? paa - pha : 0;
     const int nb = pab > phb ? pab - phb : 0;
     for (int t = 0; t < na + nb; ++t) {
-        const bool top = t >= na;
-        const int q = top ? phb + (t - na) : pha + t;
-        const double e = ptau[q] * lc - (top ? zb : za);
-        const T K = K_cut<T>(S, ptf[q], pinv[q], T(e));
-        const T Ks = top ? -K : K;
+        T e, dY[NBAT];
+        const int q = adj_straddle<T, NBAT>(t, na, pha, phb, ptau, lc, za, zb, Y, ystride, e, dY);
+        const T K = K_cut<T>(S, ptf[q], pinv[q], e);
 #pragma unroll
-        for (int b = 0; b < NBAT; ++b) sum[b] += Ks * (Y[b * ystride + q - 1] - Y[b * ystride + q]);
+        for (int b = 0; b < NBAT; ++b) sum[b] += K * dY[b];
     }
 }
 

@@ -19,23 +19,98 @@
 // at the end through LDS.  The top detector edge (plane nv) has no lane: its
 // G is summed lane-parallel over the strip's pixels in a fixed order.
 #include "sm_internal.h"
+#include "sm_wave.h"
 
 namespace smk {
 
 constexpr int kFwdChunk = 64;  // strip records staged in LDS at a time
 
+// LDS stride of a staged record.
+template <typename T>
+constexpr size_t rec_stride()
+{
+    return sizeof(Rec<T>);
+}
+
+// Straddle jobs a wave can hold: 128 (evaluated once 64 are pending) or, when
+// LDS is short (many rows), 64 (evaluated before every ballot round); at most
+// kRounds ballot rounds are kept between evaluations.
+constexpr int kQueueMax = 128;
+constexpr int kRounds = 32;
+
+template <typename T>
+__device__ __forceinline__ const Rec<T> &staged(const unsigned char *rbuf, int e)
+{
+    return *reinterpret_cast<const Rec<T> *>(rbuf + (size_t)e * rec_stride<T>());
+}
+
+// Evaluate the queued straddle jobs of this wave and add every lane's own
+// results (in queue order) to its accumulators.
+template <typename T, int NBAT>
+__device__ __forceinline__ void fwd_flush(const unsigned char *rbuf, const T *ptf, const T *pinv,
+                                          const unsigned *jobs, const T *ev, T *res,
+                                          const JobRound *rounds, int &pending, int &nrounds,
+                                          int lane, T (&acc1)[NBAT], T (&acc2)[NBAT])
+{
+    // job s: record e, plane q, face height ev[s]; res[s] holds x_j - x_{j-1}
+    wave_sync();
+    for (int s = lane; s < pending; s += 64) {
+        const unsigned jb = jobs[s];
+        const int e = (int)(jb & 63u), q = (int)(jb >> 6);
+        const Rec<T> &R = staged<T>(rbuf, e);
+        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev[s]);
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) res[s * NBAT + b] *= K;
+    }
+    wave_sync();
+    T g[NBAT];
+#pragma unroll
+    for (int b = 0; b < NBAT; ++b) g[b] = T(0);
+    for (int i = 0; i < nrounds; ++i) {
+        const JobRound jr = rounds[i];
+        const unsigned long long bal = ((unsigned long long)jr.hi << 32) | jr.lo;
+        if ((bal >> lane) & 1ull) {
+            const int slot = jr.base + lane_rank(bal);
+#pragma unroll
+            for (int b = 0; b < NBAT; ++b) g[b] += res[slot * NBAT + b];
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NBAT; ++b) {
+        acc1[b] -= g[b];
+        acc2[b] += g[b];
+    }
+    pending = 0;
+    nrounds = 0;
+    wave_sync();
+}
+
 template <typename T, int NBAT>
 __global__ void __launch_bounds__(1024)
 fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
              const int *__restrict__ soff, const double *__restrict__ P, T *__restrict__ y, int B,
-             int b0)
+             int b0, int qcap)
 {
     constexpr int RCH = (int)(sizeof(Rec<T>) / 16);
     extern __shared__ __align__(16) unsigned char smem[];
     const int nthr = blockDim.x, tid = threadIdx.x;
-    Rec<T> *rbuf = reinterpret_cast<Rec<T> *>(smem);                                // kFwdChunk
-    T *ex = reinterpret_cast<T *>(smem + sizeof(Rec<T>) * kFwdChunk);               // (nthr + 1) * NBAT
-    T *red = ex + (size_t)(nthr + 1) * NBAT;                                        // nthr * NBAT
+    const int lane = tid & 63, wave = tid >> 6;
+    // LDS: staged records | per-wave job queues | exchange and reduction arrays
+    unsigned char *rbuf = smem;  // kFwdChunk records at rec_stride<T>()
+    size_t off = rec_stride<T>() * kFwdChunk;
+    const size_t qbytes = kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * (NBAT + 1));
+    unsigned char *qw = smem + off + (size_t)wave * qbytes;
+    JobRound *rounds = reinterpret_cast<JobRound *>(qw);
+    unsigned *jobs = reinterpret_cast<unsigned *>(qw + kRounds * sizeof(JobRound));
+    T *ev = reinterpret_cast<T *>(qw + kRounds * sizeof(JobRound) + qcap * sizeof(unsigned));
+    T *res = ev + qcap;
+    off += qbytes * (size_t)(nthr / 64);
+    T *ptf = reinterpret_cast<T *>(smem + off);  // nv + 1 plane slopes in T and their inverses
+    T *pinv = ptf + (G.nv + 1);
+    off += 2 * sizeof(T) * (size_t)(G.nv + 1);
+    off = (off + 15) & ~(size_t)15;
+    T *ex = reinterpret_cast<T *>(smem + off);  // (nthr + 1) * NBAT
+    T *red = ex + (size_t)(nthr + 1) * NBAT;    // nthr * NBAT
     const int nz = G.nz, nv = G.nv;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int vl = lb / G.nu, k = lb - vl * G.nu;
@@ -49,61 +124,121 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     const T cT = T(G.c);
     const size_t colstride = (size_t)(nz + 1);
 
-    // lane r: plane r is the lower edge of row r
+    // lane r: plane r is the lower edge of row r (lanes past nv carry tau = 0
+    // and queue nothing)
     const int r = tid;
     const bool active = r < nv;
     const double tau0 = active ? G.tau[r] : 0.0;
     const T tf0 = T(tau0), tf1 = T(active ? G.tau[r + 1] : 0.0);
-    const T inv0 = tf0 != T(0) ? T(1) / tf0 : T(0);
     const double tauT = G.tau[nv];
     const T tfT = T(tauT);
     const T invT = tfT != T(0) ? T(1) / tfT : T(0);
 
+    for (int q = tid; q <= nv; q += nthr) {
+        const T t = T(G.tau[q]);
+        ptf[q] = t;
+        pinv[q] = t != T(0) ? T(1) / t : T(0);
+    }
+
     T acc1[NBAT], acc2[NBAT], accT[NBAT];
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) acc1[b] = acc2[b] = accT[b] = T(0);
+    int pending = 0, nrounds = 0;
 
     for (int c0 = 0; c0 < n_ent; c0 += kFwdChunk) {
         const int cnt = n_ent - c0 < kFwdChunk ? n_ent - c0 : kFwdChunk;
         __syncthreads();  // previous chunk consumed
         {
             const uint4 *src = reinterpret_cast<const uint4 *>(Rs + c0);
-            uint4 *dst = reinterpret_cast<uint4 *>(rbuf);
-            for (int q = tid; q < cnt * RCH; q += nthr) dst[q] = src[q];
-        }
-        __syncthreads();
-        if (active) {
-            for (int e = 0; e < cnt; ++e) {
-                const Rec<T> &R = Rs[c0 + e];  // uniform fields through the scalar cache
-                const int n = R.n;
-                if (n == 0) continue;
-                const StripTab<T> S = strip_tab<T>(R.tab, rbuf[e].tab);
-                const double lc = R.lc;
-                const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
-                const double lbar = lc + (double)R.lbo;
-                const double *Pc[NBAT];
-#pragma unroll
-                for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;
-                int f;
-                T gs[NBAT];
-                plane_G<T, NBAT>(G, S, lc, lbar, Llo, Lhi, tau0, tf0, inv0, inv_c, z0c, Pc, f, gs);
-                // first voxel not wholly below plane r + 1, as its own lane finds it
-                T lo1, hi1;
-                plane_extent<T>(tf1, Llo, Lhi, lo1, hi1);
-                int fa1, fb1;
-                face_split<T>(lo1, hi1, inv_c, z0c, nz, fa1, fb1);
-                const int f1 = fa1 - 1 < 0 ? 0 : (fa1 - 1 > nz ? nz : fa1 - 1);
-                const T cA = cT * S.A;
-#pragma unroll
-                for (int b = 0; b < NBAT; ++b) {
-                    acc1[b] += cA * T(Pc[b][f1] - Pc[b][f]) - gs[b];
-                    acc2[b] += gs[b];
-                }
+            for (int q = tid; q < cnt * RCH; q += nthr) {
+                const int e = q / RCH, ch = q - e * RCH;
+                reinterpret_cast<uint4 *>(rbuf + (size_t)e * rec_stride<T>())[ch] = src[q];
             }
         }
+        __syncthreads();
+        for (int e = 0; e < cnt; ++e) {
+            const Rec<T> &R = Rs[c0 + e];  // uniform fields through the scalar cache
+            const int n = R.n;
+            if (n == 0) continue;
+            const StripTab<T> S = strip_tab<T>(R.tab, staged<T>(rbuf, e).tab);
+            const double lc = R.lc;
+            const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
+            const double lbar = lc + (double)R.lbo;
+            const double *Pc[NBAT];
+#pragma unroll
+            for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;
+            // faces: < fa wholly below plane r, fa .. je straddled, beyond above
+            T lo, hi;
+            plane_extent<T>(tf0, Llo, Lhi, lo, hi);
+            int fa, fb;
+            face_split<T>(lo, hi, inv_c, z0c, nz, fa, fb);
+            const int f = fa - 1 < 0 ? 0 : (fa - 1 > nz ? nz : fa - 1);
+            const int je = fb - 1 < nz ? fb - 1 : nz;
+            // first voxel not wholly below plane r + 1, as its own lane finds it
+            T lo1, hi1;
+            plane_extent<T>(tf1, Llo, Lhi, lo1, hi1);
+            int fa1, fb1;
+            face_split<T>(lo1, hi1, inv_c, z0c, nz, fa1, fb1);
+            const int f1 = fa1 - 1 < 0 ? 0 : (fa1 - 1 > nz ? nz : fa1 - 1);
+            // prefix sums at f .. f + 2 serve the linear term and the first straddle
+            const int f2 = f + 1 < nz ? f + 1 : nz, f3 = f + 2 < nz ? f + 2 : nz;
+            double p0[NBAT], p1[NBAT], p2[NBAT];
+            const T cA = cT * S.A;
+            const T Klin = S.A * T(tau0 * lbar - (G.z0 + (double)f * G.c));
+            const bool lin = fa >= 1 && fa <= nz;
+#pragma unroll
+            for (int b = 0; b < NBAT; ++b) {
+                p0[b] = Pc[b][f];
+                p1[b] = Pc[b][f2];
+                p2[b] = Pc[b][f3];
+                const T gs = lin ? Klin * T(p1[b] - p0[b]) : T(0);
+                acc1[b] += cA * T(Pc[b][f1] - p0[b]) - gs;
+                acc2[b] += gs;
+            }
+            // queue the straddled faces fa .. je, one ballot round per face
+            const int ns = active && je >= fa ? je - fa + 1 : 0;
+            for (int t = 0;; ++t) {
+                const bool want = t < ns;
+                const unsigned long long bal = __ballot(want);
+                if (bal == 0ull) break;
+                if (pending > qcap - 64 || nrounds == kRounds)
+                    fwd_flush<T, NBAT>(rbuf, ptf, pinv, jobs, ev, res, rounds, pending, nrounds, lane,
+                                       acc1, acc2);
+                if (want) {
+                    const int j = fa + t;
+                    const int slot = pending + lane_rank(bal);
+                    jobs[slot] = (unsigned)e | ((unsigned)r << 6);
+                    ev[slot] = T(tau0 * lc - (G.z0 + (double)j * G.c));
+#pragma unroll
+                    for (int b = 0; b < NBAT; ++b) {
+                        T xj, xm;  // x_j and x_{j-1} (zero outside the column)
+                        if (t == 0) {
+                            xm = fa >= 1 ? T(p1[b] - p0[b]) : T(0);
+                            xj = fa >= 1 ? (fa < nz ? T(p2[b] - p1[b]) : T(0)) : T(p1[b] - p0[b]);
+                        } else {
+                            const double Pj = Pc[b][j];
+                            xm = T(Pj - Pc[b][j - 1]);
+                            xj = j < nz ? T(Pc[b][j + 1] - Pj) : T(0);
+                        }
+                        res[slot * NBAT + b] = xj - xm;
+                    }
+                }
+                if (lane == 0)
+                    rounds[nrounds] = JobRound{(unsigned)bal, (unsigned)(bal >> 32), pending, 0};
+                ++nrounds;
+                pending += __popcll(bal);
+            }
+            if (pending >= 64)
+                fwd_flush<T, NBAT>(rbuf, ptf, pinv, jobs, ev, res, rounds, pending, nrounds, lane,
+                                   acc1, acc2);
+        }
+        // jobs refer to this chunk's records: evaluate them before restaging
+        if (pending > 0)
+            fwd_flush<T, NBAT>(rbuf, ptf, pinv, jobs, ev, res, rounds, pending, nrounds, lane, acc1,
+                               acc2);
         // top detector edge: lane e takes record c0 + e (fields from LDS)
         if (tid < cnt) {
-            const Rec<T> &R = rbuf[tid];
+            const Rec<T> &R = staged<T>(rbuf, tid);
             const int n = R.n;
             if (n > 0) {
                 const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
@@ -151,9 +286,22 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
 }
 
 template <typename T, int NBAT>
-static size_t fwd3d_lds(const LaunchCfg &L)
+static size_t fwd3d_lds(const LaunchCfg &L, int qcap)
 {
-    return sizeof(Rec<T>) * kFwdChunk + sizeof(T) * (size_t)(2 * L.fwd_threads + 1) * NBAT;
+    const size_t qbytes = kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * (NBAT + 1));
+    size_t lds = rec_stride<T>() * kFwdChunk + qbytes * (size_t)(L.fwd_threads / 64);
+    lds += 2 * sizeof(T) * (size_t)(L.fwd_threads + 1);  // plane tables (nv + 1 <= fwd_threads + 1)
+    lds = (lds + 15) & ~(size_t)15;
+    return lds + sizeof(T) * (size_t)(2 * L.fwd_threads + 1) * NBAT;
+}
+
+// Largest queue capacity whose LDS fits, 0 when none does.
+template <typename T, int NBAT>
+static int fwd3d_qcap(const LaunchCfg &L)
+{
+    for (int q = kQueueMax; q >= 64; q -= 64)
+        if (fwd3d_lds<T, NBAT>(L, q) <= (size_t)L.lds_budget) return q;
+    return 0;
 }
 
 template <typename T, int NBAT>
@@ -161,10 +309,11 @@ static hipError_t launch_fwd3d_t(const DevGeom &G, const LaunchCfg &L, const Rec
                                  int nvc, const Rec<T> *recs, const int *soff, const double *P,
                                  T *y, int B, int b0, hipStream_t st)
 {
-    const size_t lds = fwd3d_lds<T, NBAT>(L);
-    if (lds > (size_t)L.lds_budget) return hipErrorInvalidValue;
+    const int qcap = fwd3d_qcap<T, NBAT>(L);
+    if (qcap == 0) return hipErrorInvalidValue;
+    const size_t lds = fwd3d_lds<T, NBAT>(L, qcap);
     hipLaunchKernelGGL((fwd3d_kernel<T, NBAT>), dim3(nvc * G.nu), dim3(L.fwd_threads), lds, st, G,
-                       RL, v0, recs, soff, P, y, B, b0);
+                       RL, v0, recs, soff, P, y, B, b0, qcap);
     return hipGetLastError();
 }
 
@@ -175,15 +324,23 @@ static hipError_t launch_fwd3d_all(const DevGeom &G, const LaunchCfg &L, const R
 {
     RecPtrs RP = rec_ptrs(RL, ws, sizeof(Rec<T>));
     const Rec<T> *recs = (const Rec<T> *)RP.recs;
+    const bool fit8 = fwd3d_qcap<T, 8>(L) > 0;
+    const bool fit4 = fwd3d_qcap<T, 4>(L) > 0;
+    const bool fit2 = fwd3d_qcap<T, 2>(L) > 0;
     hipError_t e = hipSuccess;
     for (int b0 = 0; b0 < B && e == hipSuccess;) {
         const int rem = B - b0;
-        if (rem >= 8) { e = launch_fwd3d_t<T, 8>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 8; }
-        else if (rem >= 4) { e = launch_fwd3d_t<T, 4>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 4; }
-        else if (rem >= 2) { e = launch_fwd3d_t<T, 2>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 2; }
+        if (rem >= 8 && fit8) { e = launch_fwd3d_t<T, 8>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 8; }
+        else if (rem >= 4 && fit4) { e = launch_fwd3d_t<T, 4>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 4; }
+        else if (rem >= 2 && fit2) { e = launch_fwd3d_t<T, 2>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 2; }
         else { e = launch_fwd3d_t<T, 1>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 1; }
     }
     return e;
+}
+
+bool fwd3d_fits(const LaunchCfg &L, bool fp64)
+{
+    return fp64 ? fwd3d_qcap<double, 1>(L) > 0 : fwd3d_qcap<float, 1>(L) > 0;
 }
 
 hipError_t launch_fwd3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,

@@ -85,6 +85,8 @@ hipError_t launch_fwd3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &R
 hipError_t launch_back3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,
                          int v0, int nvc, void *ws, const void *y, void *xt, int B, bool first,
                          hipStream_t st);
+// Whether the smallest forward configuration (single batch element) fits LDS.
+bool fwd3d_fits(const LaunchCfg &L, bool fp64);
 // LDS bytes of the smallest adjoint configuration (single batch element).
 size_t back3d_lds_min(const DevGeom &G, const LaunchCfg &L, bool fp64);
 hipError_t launch_fwd2d(const DevGeom &G, bool fp64, const void *x, void *y, int B,

@@ -32,6 +32,12 @@ def test_results_equal_alone_and_in_the_mix():
     print("[case] serving mix", flush=True)
     reqs = serve.make_requests(48, 500.0, 3, torch.device(DEV), mix=MIX, iters=5,
                                geometry=tiny_geometry, views=(30, 60))
+    # a burst of same-geometry requests waiting together at the first
+    # admission, so that one batched launch is certain whatever the timing
+    g = tiny_geometry("3d32", 30)
+    ys = [torch.rand(g.sino_shape, generator=torch.Generator(device=DEV).manual_seed(40 + i),
+                     device=DEV) for i in range(5)]
+    reqs += [serve.Request(100 + i, "3d32/burst", g, "cg", ys[i], 0.0, iters=5) for i in range(5)]
     probe = serve.Server(DEV)
     probe.prepare(reqs)
     biggest = max(probe.footprint(r, 1) for r in reqs)
