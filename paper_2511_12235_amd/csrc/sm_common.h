@@ -71,6 +71,22 @@ struct alignas(16) Rec {
     T tab[MAXV][4];
 };
 
+// Stride of a strip record staged in LDS.  Lanes that gather different
+// records read the same field offset; a stride of a whole number of 128-byte
+// lines would put that field of every record in the same LDS bank, so such
+// records get 16 bytes of padding.
+template <typename T>
+constexpr size_t lds_rec_stride()
+{
+    return sizeof(Rec<T>) % 128 == 0 ? sizeof(Rec<T>) + 16 : sizeof(Rec<T>);
+}
+
+template <typename T>
+__device__ __forceinline__ const Rec<T> &lds_rec(const unsigned char *base, int i)
+{
+    return *reinterpret_cast<const Rec<T> *>(base + (size_t)i * lds_rec_stride<T>());
+}
+
 __host__ __device__ inline double dmin_(double a, double b) { return a < b ? a : b; }
 __host__ __device__ inline double dmax_(double a, double b) { return a > b ? a : b; }
 
@@ -174,8 +190,8 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
             bd[j] = dmax_(lo, hi);
         }
     }
-    // polygon edges (depth-ordered end points)
-    double ea[MAXV], eb[MAXV], ta[MAXV], tb[MAXV];
+    // polygon edges (depth-ordered end points) and their lateral slopes
+    double ea[MAXV], eb[MAXV], ta[MAXV], tb[MAXV], sl[MAXV];
 #pragma unroll
     for (int e = 0; e < MAXV; ++e) {
         const double2 p = ws[e < m ? e : 0];
@@ -185,6 +201,7 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
         eb[e] = sw ? p.x : q.x;
         ta[e] = sw ? q.y : p.y;
         tb[e] = sw ? p.y : q.y;
+        sl[e] = eb[e] > ea[e] ? (tb[e] - ta[e]) / (eb[e] - ea[e]) : 0.0;
     }
     // chord width at each breakpoint: extent in t' of the polygon's section at
     // that depth; an edge of zero depth extent contributes both end points
@@ -201,7 +218,7 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
                     tmin = dmin_(tmin, dmin_(ta[e], tb[e]));
                     tmax = dmax_(tmax, dmax_(ta[e], tb[e]));
                 } else {
-                    const double tq = ta[e] + (tb[e] - ta[e]) * ((dq - ea[e]) / (eb[e] - ea[e]));
+                    const double tq = ta[e] + sl[e] * (dq - ea[e]);
                     tmin = dmin_(tmin, tq);
                     tmax = dmax_(tmax, tq);
                 }

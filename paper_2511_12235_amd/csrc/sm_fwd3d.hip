@@ -25,42 +25,41 @@ namespace smk {
 
 constexpr int kFwdChunk = 64;  // strip records staged in LDS at a time
 
-// LDS stride of a staged record.
-template <typename T>
-constexpr size_t rec_stride()
-{
-    return sizeof(Rec<T>);
-}
-
 // Straddle jobs a wave can hold: 128 (evaluated once 64 are pending) or, when
 // LDS is short (many rows), 64 (evaluated before every ballot round); at most
-// kRounds ballot rounds are kept between evaluations.
+// kRounds ballot rounds are kept between evaluations.  A job is one word:
+// staged record (bits 0-5), plane r (bits 6-16) and face j (bits 17-27); the
+// evaluating lane gathers the face height and the voxel difference itself.
 constexpr int kQueueMax = 128;
 constexpr int kRounds = 32;
 
-template <typename T>
-__device__ __forceinline__ const Rec<T> &staged(const unsigned char *rbuf, int e)
-{
-    return *reinterpret_cast<const Rec<T> *>(rbuf + (size_t)e * rec_stride<T>());
-}
-
-// Evaluate the queued straddle jobs of this wave and add every lane's own
-// results (in queue order) to its accumulators.
+// Evaluate the queued straddle jobs of this wave, K_r(z_j) (x_j - x_{j-1}),
+// and add every lane's own results (in queue order) to its accumulators.
 template <typename T, int NBAT>
-__device__ __forceinline__ void fwd_flush(const unsigned char *rbuf, const T *ptf, const T *pinv,
-                                          const unsigned *jobs, const T *ev, T *res,
-                                          const JobRound *rounds, int &pending, int &nrounds,
-                                          int lane, T (&acc1)[NBAT], T (&acc2)[NBAT])
+__device__ __forceinline__ void fwd_flush(const DevGeom &G, const unsigned char *rbuf,
+                                          const double *ptau, const T *ptf, const T *pinv,
+                                          const double *__restrict__ P, int B, int b0,
+                                          const unsigned *jobs, T *res, const JobRound *rounds,
+                                          int &pending, int &nrounds, int lane, T (&acc1)[NBAT],
+                                          T (&acc2)[NBAT])
 {
-    // job s: record e, plane q, face height ev[s]; res[s] holds x_j - x_{j-1}
     wave_sync();
+    const int nz = G.nz;
+    const size_t colstride = (size_t)(nz + 1);
     for (int s = lane; s < pending; s += 64) {
         const unsigned jb = jobs[s];
-        const int e = (int)(jb & 63u), q = (int)(jb >> 6);
-        const Rec<T> &R = staged<T>(rbuf, e);
-        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev[s]);
+        const int e = (int)(jb & 63u), q = (int)((jb >> 6) & 2047u), j = (int)((jb >> 17) & 2047u);
+        const Rec<T> &R = lds_rec<T>(rbuf, e);
+        const T ev = T(ptau[q] * R.lc - (G.z0 + (double)j * G.c));
+        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev);
 #pragma unroll
-        for (int b = 0; b < NBAT; ++b) res[s * NBAT + b] *= K;
+        for (int b = 0; b < NBAT; ++b) {
+            const double *Pc = P + ((size_t)R.pix * B + b0 + b) * colstride;
+            const double Pj = Pc[j];
+            const T xj = j < nz ? T(Pc[j + 1] - Pj) : T(0);  // x_j and x_{j-1}, zero outside
+            const T xm = j >= 1 ? T(Pj - Pc[j - 1]) : T(0);
+            res[s * NBAT + b] = K * (xj - xm);
+        }
     }
     wave_sync();
     T g[NBAT];
@@ -96,16 +95,17 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     const int nthr = blockDim.x, tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     // LDS: staged records | per-wave job queues | exchange and reduction arrays
-    unsigned char *rbuf = smem;  // kFwdChunk records at rec_stride<T>()
-    size_t off = rec_stride<T>() * kFwdChunk;
-    const size_t qbytes = kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * (NBAT + 1));
+    unsigned char *rbuf = smem;  // kFwdChunk records at lds_rec_stride<T>()
+    size_t off = lds_rec_stride<T>() * kFwdChunk;
+    const size_t qbytes = kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * NBAT);
     unsigned char *qw = smem + off + (size_t)wave * qbytes;
     JobRound *rounds = reinterpret_cast<JobRound *>(qw);
     unsigned *jobs = reinterpret_cast<unsigned *>(qw + kRounds * sizeof(JobRound));
-    T *ev = reinterpret_cast<T *>(qw + kRounds * sizeof(JobRound) + qcap * sizeof(unsigned));
-    T *res = ev + qcap;
+    T *res = reinterpret_cast<T *>(qw + kRounds * sizeof(JobRound) + qcap * sizeof(unsigned));
     off += qbytes * (size_t)(nthr / 64);
-    T *ptf = reinterpret_cast<T *>(smem + off);  // nv + 1 plane slopes in T and their inverses
+    double *ptau = reinterpret_cast<double *>(smem + off);  // nv + 1 plane slopes (FP64)
+    off += sizeof(double) * (size_t)(G.nv + 1);
+    T *ptf = reinterpret_cast<T *>(smem + off);  // the slopes in T and their inverses
     T *pinv = ptf + (G.nv + 1);
     off += 2 * sizeof(T) * (size_t)(G.nv + 1);
     off = (off + 15) & ~(size_t)15;
@@ -135,7 +135,9 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     const T invT = tfT != T(0) ? T(1) / tfT : T(0);
 
     for (int q = tid; q <= nv; q += nthr) {
-        const T t = T(G.tau[q]);
+        const double td = G.tau[q];
+        const T t = T(td);
+        ptau[q] = td;
         ptf[q] = t;
         pinv[q] = t != T(0) ? T(1) / t : T(0);
     }
@@ -152,7 +154,7 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             const uint4 *src = reinterpret_cast<const uint4 *>(Rs + c0);
             for (int q = tid; q < cnt * RCH; q += nthr) {
                 const int e = q / RCH, ch = q - e * RCH;
-                reinterpret_cast<uint4 *>(rbuf + (size_t)e * rec_stride<T>())[ch] = src[q];
+                reinterpret_cast<uint4 *>(rbuf + (size_t)e * lds_rec_stride<T>())[ch] = src[q];
             }
         }
         __syncthreads();
@@ -160,7 +162,7 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             const Rec<T> &R = Rs[c0 + e];  // uniform fields through the scalar cache
             const int n = R.n;
             if (n == 0) continue;
-            const StripTab<T> S = strip_tab<T>(R.tab, staged<T>(rbuf, e).tab);
+            const StripTab<T> S = strip_tab<T>(R.tab, lds_rec<T>(rbuf, e).tab);
             const double lc = R.lc;
             const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
             const double lbar = lc + (double)R.lbo;
@@ -180,19 +182,16 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             int fa1, fb1;
             face_split<T>(lo1, hi1, inv_c, z0c, nz, fa1, fb1);
             const int f1 = fa1 - 1 < 0 ? 0 : (fa1 - 1 > nz ? nz : fa1 - 1);
-            // prefix sums at f .. f + 2 serve the linear term and the first straddle
-            const int f2 = f + 1 < nz ? f + 1 : nz, f3 = f + 2 < nz ? f + 2 : nz;
-            double p0[NBAT], p1[NBAT], p2[NBAT];
+            // prefix sums at f and f + 1 serve the linear term
+            const int f2 = f + 1 < nz ? f + 1 : nz;
             const T cA = cT * S.A;
             const T Klin = S.A * T(tau0 * lbar - (G.z0 + (double)f * G.c));
             const bool lin = fa >= 1 && fa <= nz;
 #pragma unroll
             for (int b = 0; b < NBAT; ++b) {
-                p0[b] = Pc[b][f];
-                p1[b] = Pc[b][f2];
-                p2[b] = Pc[b][f3];
-                const T gs = lin ? Klin * T(p1[b] - p0[b]) : T(0);
-                acc1[b] += cA * T(Pc[b][f1] - p0[b]) - gs;
+                const double p0 = Pc[b][f], p1 = Pc[b][f2];
+                const T gs = lin ? Klin * T(p1 - p0) : T(0);
+                acc1[b] += cA * T(Pc[b][f1] - p0) - gs;
                 acc2[b] += gs;
             }
             // queue the straddled faces fa .. je, one ballot round per face
@@ -202,26 +201,12 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
                 const unsigned long long bal = __ballot(want);
                 if (bal == 0ull) break;
                 if (pending > qcap - 64 || nrounds == kRounds)
-                    fwd_flush<T, NBAT>(rbuf, ptf, pinv, jobs, ev, res, rounds, pending, nrounds, lane,
-                                       acc1, acc2);
+                    fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
+                                       nrounds, lane, acc1, acc2);
                 if (want) {
-                    const int j = fa + t;
+                    const unsigned j = fa + t;
                     const int slot = pending + lane_rank(bal);
-                    jobs[slot] = (unsigned)e | ((unsigned)r << 6);
-                    ev[slot] = T(tau0 * lc - (G.z0 + (double)j * G.c));
-#pragma unroll
-                    for (int b = 0; b < NBAT; ++b) {
-                        T xj, xm;  // x_j and x_{j-1} (zero outside the column)
-                        if (t == 0) {
-                            xm = fa >= 1 ? T(p1[b] - p0[b]) : T(0);
-                            xj = fa >= 1 ? (fa < nz ? T(p2[b] - p1[b]) : T(0)) : T(p1[b] - p0[b]);
-                        } else {
-                            const double Pj = Pc[b][j];
-                            xm = T(Pj - Pc[b][j - 1]);
-                            xj = j < nz ? T(Pc[b][j + 1] - Pj) : T(0);
-                        }
-                        res[slot * NBAT + b] = xj - xm;
-                    }
+                    jobs[slot] = (unsigned)e | ((unsigned)r << 6) | (j << 17);
                 }
                 if (lane == 0)
                     rounds[nrounds] = JobRound{(unsigned)bal, (unsigned)(bal >> 32), pending, 0};
@@ -229,16 +214,16 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
                 pending += __popcll(bal);
             }
             if (pending >= 64)
-                fwd_flush<T, NBAT>(rbuf, ptf, pinv, jobs, ev, res, rounds, pending, nrounds, lane,
-                                   acc1, acc2);
+                fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
+                                   nrounds, lane, acc1, acc2);
         }
         // jobs refer to this chunk's records: evaluate them before restaging
         if (pending > 0)
-            fwd_flush<T, NBAT>(rbuf, ptf, pinv, jobs, ev, res, rounds, pending, nrounds, lane, acc1,
-                               acc2);
+            fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
+                               nrounds, lane, acc1, acc2);
         // top detector edge: lane e takes record c0 + e (fields from LDS)
         if (tid < cnt) {
-            const Rec<T> &R = staged<T>(rbuf, tid);
+            const Rec<T> &R = lds_rec<T>(rbuf, tid);
             const int n = R.n;
             if (n > 0) {
                 const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
@@ -288,9 +273,10 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
 template <typename T, int NBAT>
 static size_t fwd3d_lds(const LaunchCfg &L, int qcap)
 {
-    const size_t qbytes = kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * (NBAT + 1));
-    size_t lds = rec_stride<T>() * kFwdChunk + qbytes * (size_t)(L.fwd_threads / 64);
-    lds += 2 * sizeof(T) * (size_t)(L.fwd_threads + 1);  // plane tables (nv + 1 <= fwd_threads + 1)
+    const size_t qbytes = kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * NBAT);
+    size_t lds = lds_rec_stride<T>() * kFwdChunk + qbytes * (size_t)(L.fwd_threads / 64);
+    // plane tables (nv + 1 <= fwd_threads + 1)
+    lds += (sizeof(double) + 2 * sizeof(T)) * (size_t)(L.fwd_threads + 1);
     lds = (lds + 15) & ~(size_t)15;
     return lds + sizeof(T) * (size_t)(2 * L.fwd_threads + 1) * NBAT;
 }
