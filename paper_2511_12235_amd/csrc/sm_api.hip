@@ -14,8 +14,11 @@
 using smk::DevGeom;
 using smk::LaunchCfg;
 
-// Views per record chunk: keep the records of one chunk near 1 GiB.
-static const int64_t kRecordBudget = (int64_t)1 << 30;
+// Views per record chunk: keep the records of one chunk near 3 GiB (larger
+// chunks mean fewer launches and fewer partly filled rounds of workgroups).
+static const int64_t kRecordBudget = (int64_t)3 << 30;
+// Resident waves of one adjoint round on MI355X: 256 CUs x 4 SIMDs x 6 waves.
+static const int64_t kResidentWaves = 256 * 4 * 6;
 
 namespace {
 
@@ -257,13 +260,30 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
     for (int i = 0; i < 4; ++i) L.back_pcols[i] = 1;
     L.rspan = 1;
     // Adjoint view runs: enough workgroups x waves to fill the device for
-    // small volumes (a function of the geometry only, so results do not
-    // depend on the device).
+    // small volumes, then the run count (up to 4x that) whose waves fill the
+    // last round of resident waves best, so that no round of the launch runs
+    // a third empty.  A round is taken as kResidentWaves, the single-volume
+    // adjoint's occupancy on MI355X; the rule uses the geometry and these
+    // constants only, so results do not depend on the device.
     {
         const int64_t tiles = (int64_t)((G.nx + 3) / 4) * ((G.ny + 3) / 4);
         const int64_t waves = tiles * (L.back_threads / 64);
-        int64_t gr = (8192 + waves - 1) / (waves > 0 ? waves : 1);
-        L.back_groups = (int)(gr < 1 ? 1 : (gr > 16 ? 16 : gr));
+        const int64_t wv = waves > 0 ? waves : 1;
+        int64_t gmin = (8192 + wv - 1) / wv;
+        gmin = gmin < 1 ? 1 : (gmin > 16 ? 16 : gmin);
+        auto fill = [&](int64_t g) {
+            const int64_t tail = (wv * g) % kResidentWaves;
+            return tail == 0 ? 1.0 : (double)tail / (double)kResidentWaves;
+        };
+        int64_t best = gmin;
+        for (int64_t g = gmin; g <= 4 * gmin && g <= 16; ++g) {
+            if (fill(g) >= 0.9) {
+                best = g;
+                break;
+            }
+            if (fill(g) > fill(best) + 1e-9) best = g;
+        }
+        L.back_groups = (int)best;
     }
     p->RL = smk::RecLayout{};
     if (e == hipSuccess && G.dim == 3) {
@@ -287,6 +307,9 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
         const int64_t per_view = (int64_t)G.nu * cap * (int64_t)rsz;
         int64_t V = kRecordBudget / (per_view > 0 ? per_view : 1);
         V = V < 1 ? 1 : (V > G.n_p ? G.n_p : V);
+        // chunks of equal size: no short last chunk with its own launch tails
+        const int64_t nchunks = (G.n_p + V - 1) / V;
+        V = (G.n_p + nchunks - 1) / nchunks;
         p->RL = smk::make_layout(cap, G.nx > G.ny ? G.nx : G.ny, (int)V, G.nu, G.nx, G.ny, rsz);
         const size_t need = smk::back3d_lds_min(G, L, precision == SM_FP64);
         if (e == hipSuccess && !smk::fwd3d_fits(L, precision == SM_FP64)) {
