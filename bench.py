@@ -21,6 +21,7 @@ Extra modes (no GPU) turn rocprofv3 CSV output into the text summaries kept
 under profiles/:
   --digest-stats KERNEL_STATS_CSV --out FILE --command "..."
   --digest-counters FETCH_CSV WRITE_CSV --kernel NAME --copy-mib N --out FILE --command "..."
+  --digest-valu COUNTER_CSV --out FILE --command "..."
 """
 import argparse
 import csv
@@ -64,6 +65,7 @@ def parse():
                          "(reference for HBM counters)")
     ap.add_argument("--digest-stats", metavar="CSV")
     ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--digest-valu", metavar="CSV")
     ap.add_argument("--kernel", default="back3d_kernel")
     ap.add_argument("--out")
     ap.add_argument("--command", default="")
@@ -168,6 +170,33 @@ def digest_counters(args):
     _write(args.out, lines)
 
 
+def digest_valu(args):
+    """Vector-instruction issue of the 3D kernels from one rocprofv3 --pmc pass
+    (SQ_INSTS_VALU, SQ_WAVES): a wave64 VALU instruction occupies its SIMD for
+    4 cycles, so issue-bound time = insts x 4 / (1024 SIMDs x 2.4 GHz)."""
+    rows = _rows(args.digest_valu)
+    lines = ["# VALU issue of the 3D kernels from one rocprofv3 --pmc pass",
+             "command: %s" % args.command,
+             "issue_fraction = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x duration)", "",
+             "%-16s %5s %12s %16s %12s %9s" % ("kernel", "calls", "avg_ms", "valu_per_call", "waves", "issue")]
+    for short in ("fwd3d_kernel", "back3d_kernel", "rec_kernel"):
+        disp = {}
+        for r in rows:
+            if short not in r["Kernel_Name"]:
+                continue
+            d = disp.setdefault(r["Dispatch_Id"], {"t": (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+        if not disp:
+            continue
+        n = len(disp)
+        t = sum(d["t"] for d in disp.values()) / n
+        v = sum(d.get("SQ_INSTS_VALU", 0.0) for d in disp.values()) / n
+        w = sum(d.get("SQ_WAVES", 0.0) for d in disp.values()) / n
+        issue = v * 4.0 / (1024 * 2.4e9 * t) if t > 0 else 0.0
+        lines.append("%-16s %5d %12.4f %16.4g %12.4g %9.3f" % (short, n, t * 1e3, v, w, issue))
+    _write(args.out, lines)
+
+
 def _write(path, lines):
     text = "\n".join(lines) + "\n"
     if path:
@@ -208,6 +237,8 @@ def main():
     args = parse()
     if args.digest_stats:
         return digest_stats(args)
+    if args.digest_valu:
+        return digest_valu(args)
     if args.digest_counters:
         return digest_counters(args)
     if args.gpus != 1:

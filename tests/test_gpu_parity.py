@@ -50,6 +50,14 @@ def geometries():
     g["cone_aniso_offset"] = wl.make_geometry(3, (17, 13, 70), (0.7, 1.3, 0.45), 9, 35.0, 25.0,
                                               (29, 83), (0.9, 0.5),
                                               det_corner=(-11.0, -20.0), corner=(-5.0, -9.0, -14.0))
+    # tall voxels under fine detector rows: up to 19 rows per voxel and view
+    g["cone_many_rows"] = wl.make_geometry(3, (10, 9, 6), (1.0, 1.1, 2.5), 7, 30.0, 30.0,
+                                           (24, 60), (1.0, 0.35))
+    # short scan: 9 seeded angles in [0.3, 0.3 + pi + fan angle), not equidistant
+    fan = 2.0 * np.arctan(12.0 / 60.0)
+    phi = np.sort(np.random.default_rng(41).uniform(0.3, 0.3 + np.pi + fan, 9))
+    g["cone_short_scan"] = wl.make_geometry(3, (14, 12, 9), (1.0, 1.0, 1.0), len(phi), 40.0, 35.0,
+                                            (30, 20), (1.1, 1.3), phi=phi)
     return g
 
 
@@ -99,7 +107,8 @@ def test_csr_pattern_and_values(name, oracle_mats):
     assert _rel(va32, W.data) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["c1_fan64", "cone_small", "cone_degenerate", "cone_aniso_offset"])
+@pytest.mark.parametrize("name", ["c1_fan64", "cone_small", "cone_degenerate", "cone_aniso_offset",
+                                  "cone_short_scan"])
 def test_footprints_bit_exact(name):
     g = GEOMS[name]
     _say("footprints", name)
@@ -108,7 +117,7 @@ def test_footprints_bit_exact(name):
         assert np.array_equal(A.footprints(v), O.footprints(g, v)), v
 
 
-@pytest.mark.parametrize("name", ["fan_odd", "cone_small", "cone_aniso_offset"])
+@pytest.mark.parametrize("name", ["fan_odd", "cone_small", "cone_aniso_offset", "cone_many_rows"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_dot_product(name, prec):
     g = GEOMS[name]
