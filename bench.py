@@ -22,6 +22,9 @@ under profiles/:
   --digest-stats KERNEL_STATS_CSV --out FILE --command "..."
   --digest-counters FETCH_CSV WRITE_CSV --kernel NAME --copy-mib N --out FILE --command "..."
   --digest-valu COUNTER_CSV --out FILE --command "..."
+A further GPU mode times the stored-W path (device CSR of W and W^T, sparse
+products) against the matrix-free operators on the 128^3 scan:
+  --stored [--config c2]
 """
 import argparse
 import csv
@@ -58,6 +61,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--config", default="c3", choices=["c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stored", action="store_true",
+                    help="time the stored-W mode beside the matrix-free operators instead")
     ap.add_argument("--cpu-views", type=int, default=0,
                     help="views in the oracle sample (default: one per oracle thread)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -232,6 +237,67 @@ def cpu_baseline(g, n_views):
                       % (g.nx, g.ny, g.nx, g.ny, g.nz, n_views, g.n_p, nnz, dt)}
 
 
+# ------------------------------------------------------------- stored W
+def stored_bench(args):
+    """Stored-W mode against the matrix-free operators on one scan: build
+    time of the device CSR pair, mean time of W x and W^T y by sparse
+    products and by the matrix-free kernels, and the bytes each product
+    streams (values + column indices + row offsets + input + output)."""
+    import numpy as np
+    import torch
+
+    from paper_2511_12235_amd import workloads as wl
+    from paper_2511_12235_amd.projector import StoredMatrix, SystemMatrix
+
+    g = wl.c3_cone256() if args.config == "c3" else wl.c2_cone128()
+    dev = torch.device("cuda:0")
+    A = SystemMatrix(g, args.precision, device=dev)
+    dt = A.dtype
+    x = torch.from_numpy(wl.ellipse_phantom(g, 10, seed=2)).to(dev, dt)
+    yin = torch.from_numpy(wl.uniform(g.sino_shape, 3)).to(dev, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = StoredMatrix(A)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    ws = A.workspace(1)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    reps = max(args.steps, 3)
+    ms_sf, ys = timed(lambda: S.forward(x), reps)
+    ms_sb, xs = timed(lambda: S.back(yin), reps)
+    ms_mf, ym = timed(lambda: A.forward(x, ws=ws), reps)
+    ms_mb, xm = timed(lambda: A.back(yin, ws=ws), reps)
+    vb = 8 if args.precision == "fp64" else 4
+    nnz = S.nnz
+    b_fwd = nnz * (4 + vb) + 8 * (A.n_rays + 1) + vb * (A.n_vox + A.n_rays)
+    b_back = nnz * (4 + vb) + 8 * (A.n_vox + 1) + vb * (A.n_vox + A.n_rays)
+    rel = lambda a, b: float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
+    res = {"mode": "stored-W vs matrix-free", "config": {"workload": "cone-beam %d^3, %d views, %dx%d detector"
+                                                          % (g.nx, g.n_p, g.det_ny, g.det_nz)},
+           "precision": args.precision, "nnz": nnz, "stored_bytes": 2 * nnz * (4 + vb),
+           "build_s": build_s,
+           "ms_forward": {"stored": ms_sf, "matrix_free": ms_mf},
+           "ms_adjoint": {"stored": ms_sb, "matrix_free": ms_mb},
+           "pairs_per_s": {"stored": 2 * nnz / ((ms_sf + ms_sb) / 1e3),
+                           "matrix_free": 2 * nnz / ((ms_mf + ms_mb) / 1e3)},
+           "stored_GBps": {"forward": b_fwd / ms_sf / 1e6, "adjoint": b_back / ms_sb / 1e6},
+           "stored_vs_matrix_free_rel_l2": {"forward": rel(ys, ym), "adjoint": rel(xs, xm)}}
+    print(json.dumps(res), flush=True)
+
+
 # -------------------------------------------------------------------- bench
 def main():
     args = parse()
@@ -241,6 +307,8 @@ def main():
         return digest_valu(args)
     if args.digest_counters:
         return digest_counters(args)
+    if args.stored:
+        return stored_bench(args)
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this library has no multi-GPU path); "
               "got --gpus %d" % args.gpus, file=sys.stderr)

@@ -133,6 +133,37 @@ sm_status sm_back(const sm_plan *plan, const void *y, void *x, int32_t batch, vo
 sm_status sm_weights_csr(const sm_plan *plan, sm_precision values, int64_t *nnz_inout,
                          int64_t *row_ptr_host, int32_t *col_idx_host, void *val_host);
 
+/* ------------------------------------------------------------------------
+ * Stored-W mode: W (Sec. I, W in R^{M x N}) or its transpose as device CSR
+ * arrays, for problems whose matrix fits in device memory (up to 2^31 - 1
+ * entries, voxels and detector elements), applied by a sparse matrix-vector
+ * product.  Same pattern rule and value precision choice as
+ * sm_weights_csr.  transposed = 0: rows are detector elements
+ * (i = (view det_nz + m_z) det_ny + m_y), columns voxels; transposed = 1:
+ * rows are voxels, columns detector elements.  Columns ascend within a row.
+ * ------------------------------------------------------------------------ */
+
+/* Number of entries of W (or W^T, the same number).  Allocates and frees
+ * temporary device buffers and synchronises the current device. */
+sm_status sm_stored_count(const sm_plan *plan, int32_t transposed, int64_t *nnz);
+
+/* Fill caller-allocated device arrays: row_ptr (rows + 1 int64), col_idx (nnz
+ * int32) and val (nnz float or double, as `values`).  nnz must be the count
+ * of sm_stored_count (SM_ERANGE otherwise).  A set-up routine: it allocates
+ * and frees temporary device buffers (about 8-12 bytes per entry) and
+ * synchronises `hip_stream`. */
+sm_status sm_stored_fill(const sm_plan *plan, int32_t transposed, sm_precision values, int64_t nnz,
+                         int64_t *row_ptr, int32_t *col_idx, void *val, void *hip_stream);
+
+/* y = A x for a CSR matrix A with n_rows rows (device arrays as filled by
+ * sm_stored_fill), `batch` vectors: x + b x_stride and y + b y_stride
+ * (elements).  y is overwritten; each row is summed in a fixed order (one
+ * wavefront per row), so results are deterministic.  Stream-ordered on
+ * hip_stream; does not allocate or synchronise. */
+sm_status sm_stored_apply(int64_t n_rows, const int64_t *row_ptr, const int32_t *col_idx,
+                          const void *val, sm_precision values, const void *x, void *y,
+                          int32_t batch, int64_t x_stride, int64_t y_stride, void *hip_stream);
+
 /* Footprint boxes of every voxel in one view (eq. "relevant detectors 2d"
  * and the row bounds of Sec. III-C, with strict inequalities): for voxel j,
  * boxes_host[4 j + 0..3] = first column, last column, first row, last row of

@@ -18,7 +18,8 @@ SM_FP32, SM_FP64 = 0, 1
 
 EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_workspace_size",
             "sm_forward", "sm_back",
-            "sm_weights_csr", "sm_footprints", "sm_solver_workspace_size", "sm_power_norm",
+            "sm_weights_csr", "sm_stored_count", "sm_stored_fill", "sm_stored_apply",
+            "sm_footprints", "sm_solver_workspace_size", "sm_power_norm",
             "sm_cgls", "sm_nag", "sm_timing_enable", "sm_timing_read",
             "sm_status_str", "sm_last_error")
 
@@ -83,6 +84,13 @@ def lib():
         L.sm_back.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_int64, vp]
         L.sm_weights_csr.restype = C.c_int
         L.sm_weights_csr.argtypes = [vp, C.c_int, i64p, i64p, i32p, vp]
+        L.sm_stored_count.restype = C.c_int
+        L.sm_stored_count.argtypes = [vp, C.c_int32, i64p]
+        L.sm_stored_fill.restype = C.c_int
+        L.sm_stored_fill.argtypes = [vp, C.c_int32, C.c_int, C.c_int64, vp, vp, vp, vp]
+        L.sm_stored_apply.restype = C.c_int
+        L.sm_stored_apply.argtypes = [C.c_int64, vp, vp, vp, C.c_int, vp, vp, C.c_int32, C.c_int64,
+                                      C.c_int64, vp]
         L.sm_footprints.restype = C.c_int
         L.sm_footprints.argtypes = [vp, C.c_int32, i32p]
         dp = C.POINTER(C.c_double)

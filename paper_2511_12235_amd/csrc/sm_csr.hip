@@ -218,6 +218,45 @@ __global__ void csr_fill_kernel(DevGeom G, double tau_keep, const int64_t *row_p
     }
 }
 
+// Rows of W^T (one per voxel): entry counts per voxel, one atomic per
+// (view, voxel) work-item.
+__global__ void csr_count_vox_kernel(DevGeom G, double tau_keep, int32_t *vox_cnt)
+{
+    const int64_t nvox = (int64_t)G.nx * G.ny * G.nz;
+    const int64_t n = nvox * G.n_p;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int view = (int)(q / nvox);
+        const int64_t j = q - (int64_t)view * nvox;
+        const int ix = (int)(j % G.nx), iy = (int)((j / G.nx) % G.ny), iz = (int)(j / ((int64_t)G.nx * G.ny));
+        int c = 0;
+        voxel_view_weights(G, view, ix, iy, iz, tau_keep, false, [&](int64_t, double, float) { ++c; });
+        if (c > 0) atomicAdd(&vox_cnt[j], c);
+    }
+}
+
+// Fill the rows of W^T (column = detector element); the order within a row
+// is settled by the segmented sort that follows.
+template <typename V>
+__global__ void csr_fill_vox_kernel(DevGeom G, double tau_keep, const int64_t *row_ptr,
+                                    int32_t *cursor, int32_t *cols, V *vals)
+{
+    const int64_t nvox = (int64_t)G.nx * G.ny * G.nz;
+    const int64_t n = nvox * G.n_p;
+    const bool want32 = sizeof(V) == 4;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int view = (int)(q / nvox);
+        const int64_t j = q - (int64_t)view * nvox;
+        const int ix = (int)(j % G.nx), iy = (int)((j / G.nx) % G.ny), iz = (int)(j / ((int64_t)G.nx * G.ny));
+        voxel_view_weights(G, view, ix, iy, iz, tau_keep, want32, [&](int64_t i, double w, float w32) {
+            const int64_t pos = row_ptr[j] + atomicAdd(&cursor[j], 1);
+            cols[pos] = (int32_t)i;
+            vals[pos] = want32 ? (V)w32 : (V)w;
+        });
+    }
+}
+
 template <typename V>
 __global__ void csr_sort_kernel(const int64_t *row_ptr, int64_t n_rows, int32_t *cols, V *vals)
 {
@@ -293,6 +332,29 @@ hipError_t launch_csr_fill(const DevGeom &G, bool fp64_vals, double tau_keep,
     else
         hipLaunchKernelGGL(csr_fill_kernel<float>, grid, dim3(128), 0, st, G, tau_keep, row_ptr,
                            cursor, cols, (float *)vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_count_vox(const DevGeom &G, double tau_keep, int32_t *vox_cnt, hipStream_t st)
+{
+    const int64_t n = (int64_t)G.nx * G.ny * G.nz * G.n_p;
+    hipLaunchKernelGGL(csr_count_vox_kernel, stride_grid(n, 128), dim3(128), 0, st, G, tau_keep,
+                       vox_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_fill_vox(const DevGeom &G, bool fp64_vals, double tau_keep,
+                               const int64_t *row_ptr, int32_t *cursor, int32_t *cols, void *vals,
+                               hipStream_t st)
+{
+    const int64_t n = (int64_t)G.nx * G.ny * G.nz * G.n_p;
+    const dim3 grid = stride_grid(n, 128);
+    if (fp64_vals)
+        hipLaunchKernelGGL(csr_fill_vox_kernel<double>, grid, dim3(128), 0, st, G, tau_keep,
+                           row_ptr, cursor, cols, (double *)vals);
+    else
+        hipLaunchKernelGGL(csr_fill_vox_kernel<float>, grid, dim3(128), 0, st, G, tau_keep,
+                           row_ptr, cursor, cols, (float *)vals);
     return hipGetLastError();
 }
 

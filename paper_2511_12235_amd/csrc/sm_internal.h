@@ -105,5 +105,10 @@ hipError_t launch_csr_fill(const DevGeom &G, bool fp64_vals, double tau_keep,
 hipError_t launch_csr_sort(const int64_t *row_ptr, int64_t n_rows, int32_t *cols, void *vals,
                            bool fp64_vals, hipStream_t st);
 hipError_t launch_scan_counts(const int32_t *cnt, int64_t n, int64_t *row_ptr, hipStream_t st);
+// rows of W^T (one per voxel), filled in no particular order within a row
+hipError_t launch_csr_count_vox(const DevGeom &G, double tau_keep, int32_t *vox_cnt, hipStream_t st);
+hipError_t launch_csr_fill_vox(const DevGeom &G, bool fp64_vals, double tau_keep,
+                               const int64_t *row_ptr, int32_t *cursor, int32_t *cols, void *vals,
+                               hipStream_t st);
 
 }  // namespace smk

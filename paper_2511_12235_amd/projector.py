@@ -247,3 +247,55 @@ class Projection(torch.autograd.Function):
 
 def project(x: torch.Tensor, A: SystemMatrix) -> torch.Tensor:
     return Projection.apply(x, A)
+
+
+class StoredMatrix:
+    """Stored-W mode: W and W^T of a plan as device CSR arrays
+    (sm_stored_fill), applied by sparse matrix-vector products
+    (sm_stored_apply).  For problems whose matrix fits in device memory; the
+    arrays take about (4 + value bytes) per entry and per orientation."""
+
+    def __init__(self, A: SystemMatrix, values: str | None = None):
+        self.A = A
+        self.values = values or A.precision
+        self.dtype, self._vp = _dtype_of(self.values)
+        L = _lib.lib()
+        n = C.c_int64()
+        with torch.cuda.device(A.device):
+            _lib.check(L.sm_stored_count(A._plan, 0, C.byref(n)), "sm_stored_count")
+        self.nnz = n.value
+        self.W = self._fill(0, A.n_rays)
+        self.Wt = self._fill(1, A.n_vox)
+
+    def _fill(self, transposed: int, rows: int):
+        dev = self.A.device
+        ptr = torch.empty(rows + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(self.nnz, 1), dtype=self.dtype, device=dev)
+        st = torch.cuda.current_stream(dev).cuda_stream
+        _lib.check(_lib.lib().sm_stored_fill(self.A._plan, transposed, self._vp, self.nnz, ptr.data_ptr(),
+                                             col.data_ptr(), val.data_ptr(), st), "sm_stored_fill")
+        return ptr, col, val
+
+    def _apply(self, M, x: torch.Tensor, rows: int, cols: int, out_shape) -> torch.Tensor:
+        if x.device != self.A.device or x.dtype != self.dtype or not x.is_contiguous():
+            raise ValueError("input must be a contiguous %s tensor on %s" % (self.dtype, self.A.device))
+        B = x.numel() // cols
+        if B * cols != x.numel():
+            raise ValueError("input size is not a multiple of %d" % cols)
+        y = torch.empty((B,) + out_shape if x.numel() != cols else out_shape, dtype=self.dtype,
+                        device=self.A.device)
+        ptr, col, val = M
+        st = torch.cuda.current_stream(self.A.device).cuda_stream
+        _lib.check(_lib.lib().sm_stored_apply(rows, ptr.data_ptr(), col.data_ptr(), val.data_ptr(), self._vp,
+                                              x.data_ptr(), y.data_ptr(), B, cols, rows, st),
+                   "sm_stored_apply")
+        return y
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        """y = W x (volume(s) in, sinogram(s) out)."""
+        return self._apply(self.W, x, self.A.n_rays, self.A.n_vox, self.A.sino_shape)
+
+    def back(self, y: torch.Tensor) -> torch.Tensor:
+        """x = W^T y."""
+        return self._apply(self.Wt, y, self.A.n_vox, self.A.n_rays, self.A.vol_shape)
