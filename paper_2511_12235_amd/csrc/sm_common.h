@@ -105,47 +105,42 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
     const double tc = yc * cp - xc * sp;
     const double ha = 0.5 * G.a, hb = 0.5 * G.b;
 
-    // pixel corners in cyclic order, local (depth, lateral)
-    double cd[4], ct[4];
-    {
-        const double qx[4] = {-ha, ha, ha, -ha};
-        const double qy[4] = {-hb, -hb, hb, hb};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            cd[j] = -(qx[j] * cp + qy[j] * sp);
-            ct[j] = qy[j] * cp - qx[j] * sp;
-        }
-    }
     // column planes: t' - mu l' + eps = 0 with mu = u / D, eps = tc - mu lc
     const double mu0 = (G.u0 + (double)k * G.du) / G.D;
     const double mu1 = (G.u0 + (double)(k + 1) * G.du) / G.D;
     const double ep0 = tc - mu0 * lc, ep1 = tc - mu1 * lc;
-    double g0[4], g1[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        g0[j] = ct[j] - mu0 * cd[j] + ep0;  // >= 0: u >= u_k
-        g1[j] = ct[j] - mu1 * cd[j] + ep1;  // <= 0: u <= u_{k+1}
-    }
-
-    // polygon vertices in cyclic order: kept corners and crossings in edge order
+    // pixel corner j in cyclic order, local (depth, lateral), and its signed
+    // distances to the two column planes (>= 0: u >= u_k; <= 0: u <= u_k+1)
+    auto corner = [&](int j, double &cd, double &ct, double &g0, double &g1) {
+        const double qx = (j == 1 || j == 2) ? ha : -ha;
+        const double qy = j >= 2 ? hb : -hb;
+        cd = -(qx * cp + qy * sp);
+        ct = qy * cp - qx * sp;
+        g0 = ct - mu0 * cd + ep0;
+        g1 = ct - mu1 * cd + ep1;
+    };
+    // polygon vertices in cyclic order: kept corners and crossings in edge
+    // order (one edge at a time, so that few values stay live)
     int m = 0;
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < 4; ++j) {
-        const int jn = (j + 1) & 3;
-        if (g0[j] >= 0.0 && g1[j] <= 0.0) {
-            if (m < 8) ws[m] = make_double2(cd[j], ct[j]);
+        double cdj, ctj, g0j, g1j, cdn, ctn, g0n, g1n;
+        corner(j, cdj, ctj, g0j, g1j);
+        corner((j + 1) & 3, cdn, ctn, g0n, g1n);
+        if (g0j >= 0.0 && g1j <= 0.0) {
+            if (m < 8) ws[m] = make_double2(cdj, ctj);
             ++m;
         }
         double s0 = -1.0, s1 = -1.0;
-        if ((g0[j] > 0.0 && g0[jn] < 0.0) || (g0[j] < 0.0 && g0[jn] > 0.0)) s0 = g0[j] / (g0[j] - g0[jn]);
-        if ((g1[j] > 0.0 && g1[jn] < 0.0) || (g1[j] < 0.0 && g1[jn] > 0.0)) s1 = g1[j] / (g1[j] - g1[jn]);
+        if ((g0j > 0.0 && g0n < 0.0) || (g0j < 0.0 && g0n > 0.0)) s0 = g0j / (g0j - g0n);
+        if ((g1j > 0.0 && g1n < 0.0) || (g1j < 0.0 && g1n > 0.0)) s1 = g1j / (g1j - g1n);
         const double sa = dmin_(s0, s1), sb = dmax_(s0, s1);
         if (sa >= 0.0) {
-            if (m < 8) ws[m] = make_double2(cd[j] + sa * (cd[jn] - cd[j]), ct[j] + sa * (ct[jn] - ct[j]));
+            if (m < 8) ws[m] = make_double2(cdj + sa * (cdn - cdj), ctj + sa * (ctn - ctj));
             ++m;
         }
         if (sb >= 0.0) {
-            if (m < 8) ws[m] = make_double2(cd[j] + sb * (cd[jn] - cd[j]), ct[j] + sb * (ct[jn] - ct[j]));
+            if (m < 8) ws[m] = make_double2(cdj + sb * (cdn - cdj), ctj + sb * (ctn - ctj));
             ++m;
         }
     }
@@ -190,42 +185,48 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
             bd[j] = dmax_(lo, hi);
         }
     }
-    // polygon edges (depth-ordered end points) and their lateral slopes
-    double ea[MAXV], eb[MAXV], ta[MAXV], tb[MAXV], sl[MAXV];
+    // the farthest breakpoint (static indices only: no scratch)
+    double dlast = bd[0];
 #pragma unroll
-    for (int e = 0; e < MAXV; ++e) {
-        const double2 p = ws[e < m ? e : 0];
-        const double2 q = ws[(e + 1 < m) ? e + 1 : 0];
-        const bool sw = p.x > q.x;
-        ea[e] = sw ? q.x : p.x;
-        eb[e] = sw ? p.x : q.x;
-        ta[e] = sw ? q.y : p.y;
-        tb[e] = sw ? p.y : q.y;
-        sl[e] = eb[e] > ea[e] ? (tb[e] - ta[e]) / (eb[e] - ea[e]) : 0.0;
-    }
+    for (int i = 1; i < MAXV; ++i)
+        if (i < m) dlast = bd[i];
     // chord width at each breakpoint: extent in t' of the polygon's section at
     // that depth; an edge of zero depth extent contributes both end points
-    // (the inner limit at an extreme depth)
-    double bw[MAXV];
+    // (the inner limit at an extreme depth).  One edge at a time, updating
+    // the extremes of every breakpoint, so that few values stay live.
+    double tmn[MAXV], tmx[MAXV];
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
-        double tmin = 1e300, tmax = -1e300;
-        const double dq = bd[i];
+        tmn[i] = 1e300;
+        tmx[i] = -1e300;
+    }
+#pragma unroll 1
+    for (int e = 0; e < m; ++e) {
+        const double2 p = ws[e];
+        const double2 q = ws[e + 1 < m ? e + 1 : 0];
+        const bool sw = p.x > q.x;
+        const double ea = sw ? q.x : p.x, eb = sw ? p.x : q.x;
+        const double ta = sw ? q.y : p.y, tb = sw ? p.y : q.y;
+        const bool flat = eb == ea;
+        const double sl = flat ? 0.0 : (tb - ta) / (eb - ea);
 #pragma unroll
-        for (int e = 0; e < MAXV; ++e) {
-            if (e < m && dq >= ea[e] && dq <= eb[e]) {
-                if (eb[e] == ea[e]) {
-                    tmin = dmin_(tmin, dmin_(ta[e], tb[e]));
-                    tmax = dmax_(tmax, dmax_(ta[e], tb[e]));
+        for (int i = 0; i < MAXV; ++i) {
+            const double dq = bd[i];
+            if (dq >= ea && dq <= eb) {
+                if (flat) {
+                    tmn[i] = dmin_(tmn[i], dmin_(ta, tb));
+                    tmx[i] = dmax_(tmx[i], dmax_(ta, tb));
                 } else {
-                    const double tq = ta[e] + sl[e] * (dq - ea[e]);
-                    tmin = dmin_(tmin, tq);
-                    tmax = dmax_(tmax, tq);
+                    const double tq = ta + sl * (dq - ea);
+                    tmn[i] = dmin_(tmn[i], tq);
+                    tmx[i] = dmax_(tmx[i], tq);
                 }
             }
         }
-        bw[i] = (i < m && tmax >= tmin) ? (tmax - tmin) : 0.0;
     }
+    double bw[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) bw[i] = (i < m && tmx[i] >= tmn[i]) ? (tmx[i] - tmn[i]) : 0.0;
     // suffix moments: each slab between breakpoints is a prismatoid; its
     // integral of w is L (w_i + w_i+1) / 2 and its moment about the near end
     // L^2 (w_i / 6 + w_i+1 / 3)
@@ -245,11 +246,11 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
         const double Ddv = G.D / G.dv;
         R.lbo = T(bd[0] + S1[0] / S0[0]);
         R.kLo = T(Ddv / (lc + bd[0]));
-        R.kHi = T(Ddv / (lc + bd[m - 1]));
+        R.kHi = T(Ddv / (lc + dlast));
     }
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
-        R.tab[i][0] = T(i < m ? bd[i] : bd[m - 1]);
+        R.tab[i][0] = T(i < m ? bd[i] : dlast);
         R.tab[i][1] = T(bw[i]);
         R.tab[i][2] = T(S0[i]);
         R.tab[i][3] = T(S1[i]);

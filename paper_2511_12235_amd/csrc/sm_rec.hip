@@ -40,8 +40,10 @@ __device__ int block_scan_excl(int v, int *tmp, int &total)
     return excl;
 }
 
+// Four waves per SIMD: the FP64 polygon work is written one edge at a time so
+// that it fits 128 registers; with fewer waves the kernel idles on latency.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 rec_kernel(DevGeom G, RecLayout RL, int v0, Rec<T> *__restrict__ recs, int *__restrict__ sj0,
            int *__restrict__ soff, int2 *__restrict__ pixk)
 {
