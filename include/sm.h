@@ -98,8 +98,8 @@ sm_status sm_plan_sizes(const sm_plan *plan, int64_t *n_vox, int64_t *n_rays);
 
 /* Device workspace bytes that sm_forward / sm_back need for `batch` volumes
  * (0 in 2D).  In 3D it holds the strip records of one chunk of views (the
- * top-view polygons of Sec. III-B with their chord tables, about 3 GiB at
- * most) and one FP64 column buffer per batch element. */
+ * top-view polygons of Sec. III-B with their chord tables, at most 4 GiB)
+ * and one FP64 column buffer per batch element. */
 sm_status sm_workspace_size(const sm_plan *plan, int32_t batch, int64_t *bytes);
 
 /* Forward projection y = W x (Sec. III-B Algorithm 1 for 2D; Sec. III-C for

@@ -14,9 +14,9 @@
 using smk::DevGeom;
 using smk::LaunchCfg;
 
-// Views per record chunk: keep the records of one chunk near 3 GiB (larger
+// Views per record chunk: keep the records of one chunk under 4 GiB (larger
 // chunks mean fewer launches and fewer partly filled rounds of workgroups).
-static const int64_t kRecordBudget = (int64_t)3 << 30;
+static const int64_t kRecordBudget = (int64_t)4 << 30;
 // Resident waves of one adjoint round on MI355X: 256 CUs x 4 SIMDs x 6 waves.
 static const int64_t kResidentWaves = 256 * 4 * 6;
 
