@@ -364,7 +364,9 @@ static int64_t workspace_bytes(const sm_plan *p, int64_t batch)
     if (p->G.dim != 3) return 0;
     const int64_t npix = (int64_t)p->G.nx * p->G.ny;
     const int64_t es = p->prec == SM_FP64 ? 8 : 4;
-    const int64_t fwd = npix * batch * (int64_t)(p->G.nz + 1) * (int64_t)sizeof(double);
+    // prefix sums, then max |x| per batch element
+    const int64_t fwd = smk::align256(npix * batch * (int64_t)(p->G.nz + 1) * (int64_t)sizeof(double)) +
+                        smk::align256(batch * (int64_t)sizeof(unsigned));
     const int64_t adj = (int64_t)p->L.back_groups * npix * batch * p->G.nz * es;
     return p->RL.data_off + (fwd > adj ? fwd : adj);
 }
@@ -409,8 +411,11 @@ sm_status sm_forward(const sm_plan *p, const void *x, void *y, int32_t batch, vo
     } else {
         const smk::RecLayout &RL = p->RL;
         double *P = (double *)((char *)ws + RL.data_off);
+        const int64_t npix = (int64_t)p->G.nx * p->G.ny;
+        unsigned *xmax = (unsigned *)((char *)P + smk::align256(npix * batch * (int64_t)(p->G.nz + 1) *
+                                                                (int64_t)sizeof(double)));
         q = tm_begin(p, SM_KERNEL_PREFIX, st);
-        e = smk::launch_prefix_columns(x, P, f64, batch, p->G.nz, p->G.ny, p->G.nx, st);
+        e = smk::launch_prefix_columns(x, P, xmax, f64, batch, p->G.nz, p->G.ny, p->G.nx, st);
         tm_end(p, q, st);
         for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
             const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
@@ -419,7 +424,7 @@ sm_status sm_forward(const sm_plan *p, const void *x, void *y, int32_t batch, vo
             tm_end(p, q, st);
             if (e != hipSuccess) break;
             q = tm_begin(p, SM_KERNEL_FORWARD, st);
-            e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, ws, P, y, batch, st);
+            e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, ws, P, xmax, y, batch, st);
             tm_end(p, q, st);
         }
     }

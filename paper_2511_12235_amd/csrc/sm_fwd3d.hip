@@ -18,6 +18,18 @@
 // c A (range sum) - G_r and G_r apart; the G of the plane above is added once
 // at the end through LDS.  The top detector edge (plane nv) has no lane: its
 // G is summed lane-parallel over the strip's pixels in a fixed order.
+//
+// Straddled faces are rare and fall on the same lanes record after record, so
+// each wave queues them (ballot positions) and evaluates the queue with all 64
+// lanes.  For FP32 plans the evaluating lane rounds each term to a fixed-point
+// grid and adds it to its owner's 64-bit integer sum in LDS: integer sums do
+// not depend on the order of the atomic adds, so results stay deterministic,
+// and the owner converts its sum once at the end.  The grid is a power of two
+// chosen per workgroup from a bound on the sum of |terms| (records x straddled
+// faces x their volume x 2 max|x|, max|x| per volume from the prefix pass), so
+// the sum stays below 2^62 and each term keeps about 40 more bits than FP32
+// carries.  FP64 plans keep FP64 sums and read their results back round by
+// round.
 #include "sm_internal.h"
 #include "sm_wave.h"
 
@@ -84,12 +96,46 @@ __device__ __forceinline__ void fwd_flush(const DevGeom &G, const unsigned char 
     wave_sync();
 }
 
+// FP32 plans: evaluate the queued jobs and add each term, on the fixed-point
+// grid of its volume, to the owner lane's integer sum gacc[b * nthr + r].
+template <typename T, int NBAT>
+__device__ __forceinline__ void fwd_flush_fixed(const DevGeom &G, const unsigned char *rbuf,
+                                                const double *ptau, const T *ptf, const T *pinv,
+                                                const double *__restrict__ P, int B, int b0,
+                                                const unsigned *jobs, unsigned long long *gacc,
+                                                int nthr, const int (&esh)[NBAT], int &pending, int lane)
+{
+    wave_sync();
+    const int nz = G.nz;
+    const size_t colstride = (size_t)(nz + 1);
+    for (int s = lane; s < pending; s += 64) {
+        const unsigned jb = jobs[s];
+        const int e = (int)(jb & 63u), q = (int)((jb >> 6) & 2047u), j = (int)((jb >> 17) & 2047u);
+        const Rec<T> &R = lds_rec<T>(rbuf, e);
+        const T ev = T(ptau[q] * R.lc - (G.z0 + (double)j * G.c));
+        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev);
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) {
+            const double *Pc = P + ((size_t)R.pix * B + b0 + b) * colstride;
+            const double Pj = Pc[j];
+            const T xj = j < nz ? T(Pc[j + 1] - Pj) : T(0);  // x_j and x_{j-1}, zero outside
+            const T xm = j >= 1 ? T(Pj - Pc[j - 1]) : T(0);
+            const T v = K * (xj - xm);
+            const long long fx = __double2ll_rn(ldexp((double)v, esh[b]));
+            atomicAdd(&gacc[(size_t)b * nthr + q], (unsigned long long)fx);
+        }
+    }
+    pending = 0;
+    wave_sync();
+}
+
 template <typename T, int NBAT>
 __global__ void __launch_bounds__(1024)
 fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
-             const int *__restrict__ soff, const double *__restrict__ P, T *__restrict__ y, int B,
-             int b0, int qcap)
+             const int *__restrict__ soff, const double *__restrict__ P,
+             const unsigned *__restrict__ xmax, T *__restrict__ y, int B, int b0, int qcap)
 {
+    constexpr bool fixed = sizeof(T) == 4;  // fixed-point straddle sums (FP32 plans)
     constexpr int RCH = (int)(sizeof(Rec<T>) / 16);
     extern __shared__ __align__(16) unsigned char smem[];
     const int nthr = blockDim.x, tid = threadIdx.x;
@@ -97,10 +143,11 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     // LDS: staged records | per-wave job queues | exchange and reduction arrays
     unsigned char *rbuf = smem;  // kFwdChunk records at lds_rec_stride<T>()
     size_t off = lds_rec_stride<T>() * kFwdChunk;
-    const size_t qbytes = kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * NBAT);
+    const size_t qbytes = fixed ? (size_t)qcap * sizeof(unsigned)
+                                : kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * NBAT);
     unsigned char *qw = smem + off + (size_t)wave * qbytes;
     JobRound *rounds = reinterpret_cast<JobRound *>(qw);
-    unsigned *jobs = reinterpret_cast<unsigned *>(qw + kRounds * sizeof(JobRound));
+    unsigned *jobs = reinterpret_cast<unsigned *>(fixed ? qw : qw + kRounds * sizeof(JobRound));
     T *res = reinterpret_cast<T *>(qw + kRounds * sizeof(JobRound) + qcap * sizeof(unsigned));
     off += qbytes * (size_t)(nthr / 64);
     double *ptau = reinterpret_cast<double *>(smem + off);  // nv + 1 plane slopes (FP64)
@@ -111,6 +158,10 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     off = (off + 15) & ~(size_t)15;
     T *ex = reinterpret_cast<T *>(smem + off);  // (nthr + 1) * NBAT
     T *red = ex + (size_t)(nthr + 1) * NBAT;    // nthr * NBAT
+    off += sizeof(T) * (size_t)(2 * nthr + 1) * NBAT;
+    off = (off + 15) & ~(size_t)15;
+    // fixed-point straddle sums of every lane (FP32 plans)
+    unsigned long long *gacc = reinterpret_cast<unsigned long long *>(smem + off);
     const int nz = G.nz, nv = G.nv;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int vl = lb / G.nu, k = lb - vl * G.nu;
@@ -146,6 +197,26 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) acc1[b] = acc2[b] = accT[b] = T(0);
     int pending = 0, nrounds = 0;
+
+    // fixed-point grid 1 / scale[b]: |straddle sum| <= n_ent * faces * K * 2 max|x|,
+    // H = max|tau| * pixel diagonal being the plane's rise over a pixel, a
+    // straddled face lying within one voxel height of it (faces <= H / c + 3)
+    // and K <= a b (H + c)
+    int esh[NBAT];  // scale = 2^esh (uniform, kept in scalar registers)
+    if (fixed) {
+        const double tmx = fmax(fabs(G.tau[0]), fabs(G.tau[nv]));
+        const double H = tmx * sqrt(G.a * G.a + G.b * G.b);
+        const double bound = (double)n_ent * (H / G.c + 3.0) * (G.a * G.b * (H + G.c)) * 2.0 * (1.0 + 1e-6);
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) {
+            const float xm = __uint_as_float(xmax[b0 + b]);
+            int E = 62;
+            const double m = isfinite(xm) && xm > 0.0f ? bound * (double)xm : 0.0;
+            if (m > 0.0) frexp(m, &E);  // m < 2^E
+            esh[b] = __builtin_amdgcn_readfirstlane(62 - E);
+        }
+        for (int i = tid; i < nthr * NBAT; i += nthr) gacc[i] = 0ull;
+    }
 
     for (int c0 = 0; c0 < n_ent; c0 += kFwdChunk) {
         const int cnt = n_ent - c0 < kFwdChunk ? n_ent - c0 : kFwdChunk;
@@ -200,27 +271,44 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
                 const bool want = t < ns;
                 const unsigned long long bal = __ballot(want);
                 if (bal == 0ull) break;
-                if (pending > qcap - 64 || nrounds == kRounds)
+                if (fixed) {
+                    if (pending > qcap - 64)
+                        fwd_flush_fixed<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, gacc, nthr,
+                                                 esh, pending, lane);
+                } else if (pending > qcap - 64 || nrounds == kRounds) {
                     fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
                                        nrounds, lane, acc1, acc2);
+                }
                 if (want) {
                     const unsigned j = fa + t;
                     const int slot = pending + lane_rank(bal);
                     jobs[slot] = (unsigned)e | ((unsigned)r << 6) | (j << 17);
                 }
-                if (lane == 0)
-                    rounds[nrounds] = JobRound{(unsigned)bal, (unsigned)(bal >> 32), pending, 0};
-                ++nrounds;
+                if (!fixed) {
+                    if (lane == 0)
+                        rounds[nrounds] = JobRound{(unsigned)bal, (unsigned)(bal >> 32), pending, 0};
+                    ++nrounds;
+                }
                 pending += __popcll(bal);
             }
-            if (pending >= 64)
+            if (pending >= 64) {
+                if (fixed)
+                    fwd_flush_fixed<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, gacc, nthr, esh,
+                                             pending, lane);
+                else
+                    fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
+                                       nrounds, lane, acc1, acc2);
+            }
+        }
+        // jobs refer to this chunk's records: evaluate them before restaging
+        if (pending > 0) {
+            if (fixed)
+                fwd_flush_fixed<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, gacc, nthr, esh,
+                                         pending, lane);
+            else
                 fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
                                    nrounds, lane, acc1, acc2);
         }
-        // jobs refer to this chunk's records: evaluate them before restaging
-        if (pending > 0)
-            fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
-                               nrounds, lane, acc1, acc2);
         // top detector edge: lane e takes record c0 + e (fields from LDS)
         if (tid < cnt) {
             const Rec<T> &R = lds_rec<T>(rbuf, tid);
@@ -242,6 +330,17 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
         }
     }
 
+    if (fixed) {  // every wave's adds to this lane's sums are done
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) {
+            // a non-finite value in the volume makes the sum NaN (0 * inf)
+            const float xm = __uint_as_float(xmax[b0 + b]);
+            const T g = T(ldexp((double)(long long)gacc[(size_t)b * nthr + tid], -esh[b])) + T(0.0f * xm);
+            acc1[b] -= g;
+            acc2[b] += g;
+        }
+    }
     // y_r = acc1_r + acc2_{r+1}; acc2_nv is the fixed-order sum of accT
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) {
@@ -273,12 +372,17 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
 template <typename T, int NBAT>
 static size_t fwd3d_lds(const LaunchCfg &L, int qcap)
 {
-    const size_t qbytes = kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * NBAT);
+    constexpr bool fixed = sizeof(T) == 4;
+    const size_t qbytes = fixed ? (size_t)qcap * sizeof(unsigned)
+                                : kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * NBAT);
     size_t lds = lds_rec_stride<T>() * kFwdChunk + qbytes * (size_t)(L.fwd_threads / 64);
     // plane tables (nv + 1 <= fwd_threads + 1)
     lds += (sizeof(double) + 2 * sizeof(T)) * (size_t)(L.fwd_threads + 1);
     lds = (lds + 15) & ~(size_t)15;
-    return lds + sizeof(T) * (size_t)(2 * L.fwd_threads + 1) * NBAT;
+    lds += sizeof(T) * (size_t)(2 * L.fwd_threads + 1) * NBAT;
+    lds = (lds + 15) & ~(size_t)15;
+    if (fixed) lds += sizeof(unsigned long long) * (size_t)L.fwd_threads * NBAT;
+    return lds;
 }
 
 // Largest queue capacity whose LDS fits, 0 when none does.
@@ -293,20 +397,20 @@ static int fwd3d_qcap(const LaunchCfg &L)
 template <typename T, int NBAT>
 static hipError_t launch_fwd3d_t(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, int v0,
                                  int nvc, const Rec<T> *recs, const int *soff, const double *P,
-                                 T *y, int B, int b0, hipStream_t st)
+                                 const unsigned *xmax, T *y, int B, int b0, hipStream_t st)
 {
     const int qcap = fwd3d_qcap<T, NBAT>(L);
     if (qcap == 0) return hipErrorInvalidValue;
     const size_t lds = fwd3d_lds<T, NBAT>(L, qcap);
     hipLaunchKernelGGL((fwd3d_kernel<T, NBAT>), dim3(nvc * G.nu), dim3(L.fwd_threads), lds, st, G,
-                       RL, v0, recs, soff, P, y, B, b0, qcap);
+                       RL, v0, recs, soff, P, xmax, y, B, b0, qcap);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_fwd3d_all(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL,
-                                   int v0, int nvc, void *ws, const double *P, T *y, int B,
-                                   hipStream_t st)
+                                   int v0, int nvc, void *ws, const double *P, const unsigned *xmax,
+                                   T *y, int B, hipStream_t st)
 {
     RecPtrs RP = rec_ptrs(RL, ws, sizeof(Rec<T>));
     const Rec<T> *recs = (const Rec<T> *)RP.recs;
@@ -316,10 +420,10 @@ static hipError_t launch_fwd3d_all(const DevGeom &G, const LaunchCfg &L, const R
     hipError_t e = hipSuccess;
     for (int b0 = 0; b0 < B && e == hipSuccess;) {
         const int rem = B - b0;
-        if (rem >= 8 && fit8) { e = launch_fwd3d_t<T, 8>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 8; }
-        else if (rem >= 4 && fit4) { e = launch_fwd3d_t<T, 4>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 4; }
-        else if (rem >= 2 && fit2) { e = launch_fwd3d_t<T, 2>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 2; }
-        else { e = launch_fwd3d_t<T, 1>(G, L, RL, v0, nvc, recs, RP.soff, P, y, B, b0, st); b0 += 1; }
+        if (rem >= 8 && fit8) { e = launch_fwd3d_t<T, 8>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 8; }
+        else if (rem >= 4 && fit4) { e = launch_fwd3d_t<T, 4>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 4; }
+        else if (rem >= 2 && fit2) { e = launch_fwd3d_t<T, 2>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 2; }
+        else { e = launch_fwd3d_t<T, 1>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 1; }
     }
     return e;
 }
@@ -330,10 +434,11 @@ bool fwd3d_fits(const LaunchCfg &L, bool fp64)
 }
 
 hipError_t launch_fwd3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,
-                        int v0, int nvc, void *ws, const double *P, void *y, int B, hipStream_t st)
+                        int v0, int nvc, void *ws, const double *P, const unsigned *xmax, void *y,
+                        int B, hipStream_t st)
 {
-    if (fp64) return launch_fwd3d_all<double>(G, L, RL, v0, nvc, ws, P, (double *)y, B, st);
-    return launch_fwd3d_all<float>(G, L, RL, v0, nvc, ws, P, (float *)y, B, st);
+    if (fp64) return launch_fwd3d_all<double>(G, L, RL, v0, nvc, ws, P, nullptr, (double *)y, B, st);
+    return launch_fwd3d_all<float>(G, L, RL, v0, nvc, ws, P, xmax, (float *)y, B, st);
 }
 
 }  // namespace smk
