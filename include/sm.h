@@ -99,7 +99,7 @@ sm_status sm_plan_sizes(const sm_plan *plan, int64_t *n_vox, int64_t *n_rays);
 /* Device workspace bytes that sm_forward / sm_back need for `batch` volumes
  * (0 in 2D).  In 3D it holds the strip records of one chunk of views (the
  * top-view polygons of Sec. III-B with their chord tables, at most 4 GiB)
- * and one FP64 column buffer per batch element. */
+ * and one FP64 column buffer and one word per batch element. */
 sm_status sm_workspace_size(const sm_plan *plan, int32_t batch, int64_t *bytes);
 
 /* Forward projection y = W x (Sec. III-B Algorithm 1 for 2D; Sec. III-C for
@@ -108,7 +108,13 @@ sm_status sm_workspace_size(const sm_plan *plan, int32_t batch, int64_t *bytes);
  * of at least sm_workspace_size(batch) bytes (may be NULL when that is 0);
  * ws_bytes is its size.
  * Weights are recomputed on the fly; each is evaluated once per call and
- * applied to every batch element. */
+ * applied to every batch element.  Accuracy (SM_FP32 plans): the few volume
+ * terms of voxel faces that a detector row plane cuts are rounded to a
+ * fixed-point grid tied to max|x| of each volume and summed exactly; the grid
+ * rules out overflow and adds an absolute error per measurement of order
+ * 2^-60 R^2 a b c max|x|, R the voxel columns a detector column's beam meets
+ * (about 2^-36 a b c max|x| at 256^3), far below FP32 rounding.  A non-finite
+ * value in a volume makes its measurements NaN. */
 sm_status sm_forward(const sm_plan *plan, const void *x, void *y, int32_t batch, void *ws,
                      int64_t ws_bytes, void *hip_stream);
 
@@ -163,6 +169,40 @@ sm_status sm_stored_fill(const sm_plan *plan, int32_t transposed, sm_precision v
 sm_status sm_stored_apply(int64_t n_rows, const int64_t *row_ptr, const int32_t *col_idx,
                           const void *val, sm_precision values, const void *x, void *y,
                           int32_t batch, int64_t x_stride, int64_t y_stride, void *hip_stream);
+
+/* Line-based comparison model (Sec. IV: the line-based system matrix the
+ * paper compares against, and its complexity experiment, which averages k
+ * lines per detector element to approach the area-based matrix).  Detector
+ * element (m_y, m_z) is sampled by the k (2D) or k x k (3D) lines from the
+ * source through the detector points
+ *     u = det_y0 + (m_y + (s + 1/2) / k) dy,  v = det_z0 + (m_z + (t + 1/2) / k) dz.
+ * With the line's points alpha (D, u, v) in the view frame of Sec. III-A
+ * (alpha >= 0, alpha = 1 on the detector), voxel j holds the piece
+ * alpha in [alpha_in, alpha_out] of the line inside its closed box; on an axis
+ * the line runs parallel to, the voxel whose half-open slab [lo, hi) holds
+ * the source keeps the line.  Weight of voxel j for the element, summed over
+ * its sub-lines:
+ *   SM_LINE_LENGTH : R (alpha_out - alpha_in) / k^(dim-1), R = |(D, u, v)|
+ *                    (the mean path length: the classical line model);
+ *   SM_LINE_MEASURE: dy D (alpha_out^2 - alpha_in^2) / (2k) in 2D,
+ *                    dy dz D (alpha_out^3 - alpha_in^3) / (3k^2) in 3D (the
+ *                    midpoint rule over the element of its exact area/volume,
+ *                    which tends to W of sm_forward as k grows). */
+typedef enum { SM_LINE_LENGTH = 0, SM_LINE_MEASURE = 1 } sm_line_weight;
+#define SM_LINE_MAX_K 64
+
+/* y = W_line x for `batch` volumes, layouts and stream as sm_forward; needs
+ * no workspace and allocates nothing.  1 <= k <= SM_LINE_MAX_K.  Geometry in
+ * FP64, sums in FP64, x and y in the plan's precision.  SM_EINVAL for a bad
+ * k, weighting, batch or pointer. */
+sm_status sm_line_forward(const sm_plan *plan, int32_t k, sm_line_weight weight, const void *x,
+                          void *y, int32_t batch, void *hip_stream);
+
+/* x = W_line^T y, the exact transpose of sm_line_forward's matrix (every
+ * piece is computed with the same expressions in both directions); same
+ * arguments and errors. */
+sm_status sm_line_back(const sm_plan *plan, int32_t k, sm_line_weight weight, const void *y,
+                       void *x, int32_t batch, void *hip_stream);
 
 /* Footprint boxes of every voxel in one view (eq. "relevant detectors 2d"
  * and the row bounds of Sec. III-C, with strict inequalities): for voxel j,

@@ -140,6 +140,65 @@ def forward_rows(g, k, weight, x, rays):
     return np.array([row(g, k, weight, v, mz, my) @ xf for v, mz, my in rays])
 
 
+def column(g, k, weight, view, ix, iy, iz=0):
+    """Weights of voxel (ix, iy, iz) for every detector element of one view,
+    shape (det_nz, det_ny): the same definition, vectorised over the view's
+    sub-lines instead of the voxels."""
+    cp, sn = _trig(g, view)
+    D = g.s + g.d
+    gu = np.arange(g.det_ny * k)
+    u = g.det_y0 + (gu // k + (gu % k + 0.5) / k) * g.dy
+    if g.dim == 3:
+        gv = np.arange(g.det_nz * k)
+        v = g.det_z0 + (gv // k + (gv % k + 0.5) / k) * g.dz
+    else:
+        v = np.zeros(1)
+    U, V = np.meshgrid(u, v)  # (rows, columns) of sub-lines
+    S = (g.s * cp, g.s * sn, 0.0)
+    d = (-D * cp - U * sn, -D * sn + U * cp, V)
+    lo = np.zeros(U.shape)
+    hi = np.full(U.shape, np.inf)
+    axes = [(0, g.x0 + ix * g.a, g.x0 + (ix + 1) * g.a), (1, g.y0 + iy * g.b, g.y0 + (iy + 1) * g.b)]
+    if g.dim == 3:
+        axes.append((2, g.z0 + iz * g.c, g.z0 + (iz + 1) * g.c))
+    for ax, e0, e1 in axes:
+        da = d[ax]
+        par = da == 0.0
+        with np.errstate(divide="ignore", invalid="ignore"):
+            a1 = (e0 - S[ax]) / da
+            a2 = (e1 - S[ax]) / da
+        inside = (e0 <= S[ax]) & (S[ax] < e1)
+        lo = np.where(par, lo, np.maximum(lo, np.minimum(a1, a2)))
+        hi = np.where(par, np.where(inside, hi, -np.inf), np.minimum(hi, np.maximum(a1, a2)))
+    hit = lo < hi
+    a0 = np.where(hit, lo, 0.0)
+    a1 = np.where(hit, hi, 0.0)
+    if weight == "length":
+        R = np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+        w = R * (a1 - a0) / (k ** (g.dim - 1))
+    elif weight == "measure":
+        if g.dim == 2:
+            w = (g.dy / k) * D * (a1 ** 2 - a0 ** 2) / 2.0
+        else:
+            w = (g.dy * g.dz / k ** 2) * D * (a1 ** 3 - a0 ** 3) / 3.0
+    else:
+        raise ValueError("weight must be 'length' or 'measure'")
+    w = np.where(hit, w, 0.0)
+    kv = k if g.dim == 3 else 1
+    return w.reshape(g.det_nz, kv, g.det_ny, k).sum(axis=(1, 3))
+
+
+def back_voxels(g, k, weight, y, voxels):
+    """(W_line^T y) at the listed flat voxel indices, one voxel at a time."""
+    yv = np.asarray(y, dtype=np.float64).reshape(g.sino_shape)
+    out = []
+    for j in voxels:
+        iz, rem = divmod(int(j), g.ny * g.nx)
+        iy, ix = divmod(rem, g.nx)
+        out.append(sum(float(np.sum(column(g, k, weight, v, ix, iy, iz) * yv[v])) for v in range(g.n_p)))
+    return np.array(out)
+
+
 def grid_interval(g, S, d):
     """[alpha_in, alpha_out] of the line inside the whole grid box (one box,
     the same slab rule); used to check that the per-voxel pieces tile it."""

@@ -17,13 +17,15 @@ SM_OK, SM_EINVAL, SM_ENOMEM, SM_EDEVICE, SM_EUNSUPPORTED, SM_ERANGE = range(6)
 SM_FP32, SM_FP64 = 0, 1
 
 EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_workspace_size",
-            "sm_forward", "sm_back",
+            "sm_forward", "sm_back", "sm_line_forward", "sm_line_back",
             "sm_weights_csr", "sm_stored_count", "sm_stored_fill", "sm_stored_apply",
             "sm_footprints", "sm_solver_workspace_size", "sm_power_norm",
             "sm_cgls", "sm_nag", "sm_timing_enable", "sm_timing_read",
             "sm_status_str", "sm_last_error")
 
 SM_SOLVER_CGLS, SM_SOLVER_NAG, SM_SOLVER_POWER = range(3)
+SM_LINE_LENGTH, SM_LINE_MEASURE = range(2)
+SM_LINE_MAX_K = 64
 
 # sm_kernel ids (timing)
 KERNELS = ("records", "forward", "adjoint", "prefix", "transpose")
@@ -82,6 +84,10 @@ def lib():
         L.sm_forward.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_int64, vp]
         L.sm_back.restype = C.c_int
         L.sm_back.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_int64, vp]
+        L.sm_line_forward.restype = C.c_int
+        L.sm_line_forward.argtypes = [vp, C.c_int32, C.c_int, vp, vp, C.c_int32, vp]
+        L.sm_line_back.restype = C.c_int
+        L.sm_line_back.argtypes = [vp, C.c_int32, C.c_int, vp, vp, C.c_int32, vp]
         L.sm_weights_csr.restype = C.c_int
         L.sm_weights_csr.argtypes = [vp, C.c_int, i64p, i64p, i32p, vp]
         L.sm_stored_count.restype = C.c_int

@@ -126,6 +126,44 @@ class SystemMatrix:
 
     __matmul__ = forward
 
+    # ------------------------------------------------- line-based comparison
+    @staticmethod
+    def _line_weight(weight: str) -> int:
+        if weight == "length":
+            return _lib.SM_LINE_LENGTH
+        if weight == "measure":
+            return _lib.SM_LINE_MEASURE
+        raise ValueError("weight must be 'length' or 'measure'")
+
+    def line_forward(self, x: torch.Tensor, k: int = 1, weight: str = "length",
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+        """y = W_line x: the line-based model with k (k x k in 3D) lines per
+        detector element (sm_line_forward), on the current stream."""
+        B = self._check(x, self.vol_shape, "x")
+        shape = ((B,) if x.dim() == 4 else ()) + self.sino_shape
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=self.device)
+        elif self._check(out, self.sino_shape, "out") != B:
+            raise ValueError("out batch does not match x")
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().sm_line_forward(self._plan, int(k), self._line_weight(weight), x.data_ptr(),
+                                              out.data_ptr(), B, st), "sm_line_forward")
+        return out
+
+    def line_back(self, y: torch.Tensor, k: int = 1, weight: str = "length",
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+        """x = W_line^T y (sm_line_back), the transpose of line_forward."""
+        B = self._check(y, self.sino_shape, "y")
+        shape = ((B,) if y.dim() == 4 else ()) + self.vol_shape
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=self.device)
+        elif self._check(out, self.vol_shape, "out") != B:
+            raise ValueError("out batch does not match y")
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().sm_line_back(self._plan, int(k), self._line_weight(weight), y.data_ptr(),
+                                           out.data_ptr(), B, st), "sm_line_back")
+        return out
+
     # ---------------------------------------------------------------- solvers
     def solver_workspace(self, solver: int, batch: int = 1) -> torch.Tensor:
         n = C.c_int64()

@@ -147,6 +147,32 @@ def test_batched_equals_single(name, batch):
         assert np.array_equal(xb[i], A.back(_t(Y[i], "fp32")).cpu().numpy())
 
 
+@pytest.mark.parametrize("name", ["cone_small", "cone_many_rows", "cone_aniso_offset"])
+def test_fp32_forward_magnitudes(name, oracle_mats):
+    """The FP32 forward sums its straddle terms on a fixed-point grid set by
+    max|x| of each volume: the relative error must not depend on the scale of
+    x, volumes of very different scale share a batch, zero stays zero and a
+    non-finite voxel makes (only) its own volume's measurements NaN."""
+    g = GEOMS[name]
+    _say("fp32 magnitudes", name)
+    W = _W(name, oracle_mats)
+    A = SystemMatrix(g, "fp32", device=DEV)
+    x = wl.ellipse_phantom(g, 5, seed=7) + 0.1 * wl.uniform(g.vol_shape, 8)
+    for s in (1e-30, 1e-8, 1e8, 1e30):
+        yg = A.forward(_t(x * s, "fp32")).double().cpu().numpy()
+        assert _rel(yg.ravel(), W @ (x * s).ravel()) <= TOL["fp32"], s
+    X = np.stack([x * 1e-20, x, x * 1e20, np.zeros_like(x)])
+    yb = A.forward(_t(X, "fp32")).cpu().numpy()
+    for i in range(len(X)):
+        assert np.array_equal(yb[i], A.forward(_t(X[i], "fp32")).cpu().numpy()), i
+    assert not yb[3].any()
+    Xn = np.stack([x, x.copy()])
+    Xn[1].flat[Xn[1].size // 2] = np.nan
+    yn = A.forward(_t(Xn, "fp32")).cpu().numpy()
+    assert np.array_equal(yn[0], yb[1])
+    assert np.isnan(yn[1]).all()
+
+
 def test_deterministic_repeat():
     g = GEOMS["cone_small"]
     _say("determinism")

@@ -122,3 +122,21 @@ def test_length_weighting_is_the_mean_of_sub_line_lengths():
                 A0, A1 = LN.grid_interval(g, S, d)
                 total += (A1 - A0) * np.linalg.norm(d) / k
             assert r.sum() == pytest.approx(total, rel=1e-12, abs=1e-14)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_column_view_equals_matrix_columns(dim):
+    """The per-voxel form (vectorised over sub-lines) and the per-line form
+    (vectorised over voxels) give the same matrix."""
+    if dim == 2:
+        g = wl.make_geometry(2, (6, 5), (1.0, 1.2), 3, 25.0, 20.0, (7,), (1.3,))
+    else:
+        g = wl.make_geometry(3, (4, 3, 3), (1.0, 1.1, 0.9), 2, 25.0, 20.0, (6, 5), (1.4, 1.3))
+    k = 3
+    for weight in LN.WEIGHTS:
+        W = LN.matrix(g, k, weight).toarray()
+        for j in range(g.n_vox):
+            iz, rem = divmod(j, g.ny * g.nx)
+            iy, ix = divmod(rem, g.nx)
+            col = np.concatenate([LN.column(g, k, weight, v, ix, iy, iz).ravel() for v in range(g.n_p)])
+            np.testing.assert_allclose(col, W[:, j], rtol=1e-12, atol=1e-14)
