@@ -25,6 +25,9 @@ under profiles/:
 A further GPU mode times the stored-W path (device CSR of W and W^T, sparse
 products) against the matrix-free operators on the 128^3 scan:
   --stored [--config c2]
+and one the line-based comparison model (k lines per detector element,
+sm_line_forward / sm_line_back) against the exact operators:
+  --line [--line-ks 1,2] [--config c3]
 """
 import argparse
 import csv
@@ -65,6 +68,9 @@ def parse():
                     help="time the stored-W mode beside the matrix-free operators instead")
     ap.add_argument("--cpu-views", type=int, default=0,
                     help="views in the oracle sample (default: one per oracle thread)")
+    ap.add_argument("--line", action="store_true",
+                    help="time the line-based model (k lines per element) beside the exact operators")
+    ap.add_argument("--line-ks", default="1,2")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB "
                          "(reference for HBM counters)")
@@ -298,6 +304,55 @@ def stored_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def line_bench(args):
+    """Line-based model against the exact operators on one scan: mean time
+    of W_line x and W_line^T y for each k and weighting, the sub-lines per
+    second of the forward and the voxel-views per second of the adjoint."""
+    import torch
+
+    from paper_2511_12235_amd import workloads as wl
+    from paper_2511_12235_amd.projector import SystemMatrix
+
+    g = wl.c3_cone256() if args.config == "c3" else wl.c2_cone128()
+    dev = torch.device("cuda:0")
+    A = SystemMatrix(g, args.precision, device=dev)
+    dt = A.dtype
+    x = torch.from_numpy(wl.ellipse_phantom(g, 10, seed=2)).to(dev, dt)
+    yin = torch.from_numpy(wl.uniform(g.sino_shape, 3)).to(dev, dt)
+    ws = A.workspace(1)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(args.steps, 3)
+    rows = []
+    for k in [int(v) for v in args.line_ks.split(",")]:
+        for w in ("length", "measure"):
+            mf = timed(lambda: A.line_forward(x, k, w), reps)
+            mb = timed(lambda: A.line_back(yin, k, w), reps)
+            sub = A.n_rays * k ** (g.dim - 1)
+            rows.append({"k": k, "weight": w, "ms_forward": mf, "ms_adjoint": mb,
+                         "sub_lines_per_s": sub / (mf / 1e3),
+                         "voxel_views_per_s": A.n_vox * g.n_p / (mb / 1e3)})
+            print("line k=%d %s: forward %.2f ms, adjoint %.2f ms" % (k, w, mf, mb), file=sys.stderr, flush=True)
+    area = {"ms_forward": timed(lambda: A.forward(x, ws=ws), reps),
+            "ms_adjoint": timed(lambda: A.back(yin, ws=ws), reps)}
+    res = {"mode": "line-based vs exact", "config": {"workload": "cone-beam %d^3, %d views, %dx%d detector"
+                                                     % (g.nx, g.n_p, g.det_ny, g.det_nz)},
+           "precision": args.precision, "line": rows, "exact": area}
+    print(json.dumps(res), flush=True)
+
+
 # -------------------------------------------------------------------- bench
 def main():
     args = parse()
@@ -307,6 +362,8 @@ def main():
         return digest_valu(args)
     if args.digest_counters:
         return digest_counters(args)
+    if args.line:
+        return line_bench(args)
     if args.stored:
         return stored_bench(args)
     if args.gpus != 1:

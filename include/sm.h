@@ -269,6 +269,19 @@ sm_status sm_nag(const sm_plan *plan, const void *y, void *x, int32_t batch, int
                  double lambda, double wscale, const double *norm_dev, double *hist_dev,
                  void *ws, int64_t ws_bytes, void *hip_stream);
 
+/* sm_power_norm and sm_nag with the line-based operators of sm_line_forward /
+ * sm_line_back (k lines per element, weighting) in place of W: the solver of
+ * the line-based reconstructions the paper compares against (Sec. IV).  Same
+ * arguments, workspace (sm_solver_workspace_size of the same kind) and
+ * errors, plus SM_EINVAL for k outside [1, SM_LINE_MAX_K] or a bad weighting. */
+sm_status sm_line_power_norm(const sm_plan *plan, int32_t k, sm_line_weight weight, const void *v0,
+                             int32_t iters, double *norm_dev, void *ws, int64_t ws_bytes,
+                             void *hip_stream);
+sm_status sm_line_nag(const sm_plan *plan, int32_t k, sm_line_weight weight, const void *y, void *x,
+                      int32_t batch, int32_t iters, double lambda, double wscale,
+                      const double *norm_dev, double *hist_dev, void *ws, int64_t ws_bytes,
+                      void *hip_stream);
+
 /* Per-kernel timing, for measurement only (not part of the method).  While
  * timing is enabled on a plan, sm_forward and sm_back record a pair of HIP
  * events on their stream around every dispatch of the kernels below and add

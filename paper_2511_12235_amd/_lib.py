@@ -20,7 +20,7 @@ EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_workspace_
             "sm_forward", "sm_back", "sm_line_forward", "sm_line_back",
             "sm_weights_csr", "sm_stored_count", "sm_stored_fill", "sm_stored_apply",
             "sm_footprints", "sm_solver_workspace_size", "sm_power_norm",
-            "sm_cgls", "sm_nag", "sm_timing_enable", "sm_timing_read",
+            "sm_cgls", "sm_nag", "sm_line_power_norm", "sm_line_nag", "sm_timing_enable", "sm_timing_read",
             "sm_status_str", "sm_last_error")
 
 SM_SOLVER_CGLS, SM_SOLVER_NAG, SM_SOLVER_POWER = range(3)
@@ -110,6 +110,11 @@ def lib():
         L.sm_nag.restype = C.c_int
         L.sm_nag.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_double, C.c_double, vp, vp, vp,
                              C.c_int64, vp]
+        L.sm_line_power_norm.restype = C.c_int
+        L.sm_line_power_norm.argtypes = [vp, C.c_int32, C.c_int, vp, C.c_int32, vp, vp, C.c_int64, vp]
+        L.sm_line_nag.restype = C.c_int
+        L.sm_line_nag.argtypes = [vp, C.c_int32, C.c_int, vp, vp, C.c_int32, C.c_int32, C.c_double,
+                                  C.c_double, vp, vp, vp, C.c_int64, vp]
         L.sm_timing_enable.restype = C.c_int
         L.sm_timing_enable.argtypes = [vp, C.c_int32]
         L.sm_timing_read.restype = C.c_int

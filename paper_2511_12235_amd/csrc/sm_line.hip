@@ -19,10 +19,13 @@
 //
 // Forward: one thread per detector element walks each of its sub-lines voxel
 // by voxel, taking the plane crossings of the axes in increasing alpha; sums
-// in FP64, one store, no atomics.  Adjoint: one thread per voxel (in 3D the
-// lanes of a wave run along z, so they share the voxel column and its
-// top-view work) visits, per view, the sub-lines whose detector points fall
-// in the voxel's shadow and clips each against the voxel.  Both sides compute
+// in FP64, one store, no atomics.  Adjoint: a gather over the sub-lines whose
+// detector points fall in the voxel's shadow, each clipped against the voxel.
+// In 3D one workgroup owns a voxel column with its lanes along z: per view
+// the first wave clips the column's sub-line columns (the x and y slabs,
+// shared by every voxel of the column) into LDS, and each lane adds the z
+// slab of its own voxel for the sub-line rows of its shadow.  In 2D one
+// thread owns a pixel.  Both sides compute
 // every crossing, direction and weight with the same expressions under
 // contraction off, so a piece has one value in both directions and the pair
 // is adjoint up to the order of the sums.
@@ -36,12 +39,22 @@ struct LineCfg {
     double du_k, dv_k;  // sub-line pitch along u and v
     double wl;          // 1 / k^(dim-1)
     double wm;          // h_u D / (2k) in 2D, h_u h_v D / (3k^2) in 3D
+    int vtab;           // 3D adjoint: sub-row positions and inverses tabled in LDS
 };
+
+constexpr int kLineEntries = 16;  // sub-line columns of one view clipped per pass (3D adjoint)
+constexpr int kLineVtab = 1024;   // largest tabled sub-row count
+
+__device__ __forceinline__ double plane_coord(double o, double h, int p)
+{
+#pragma clang fp contract(off)
+    return o + (double)p * h;
+}
 
 __device__ __forceinline__ double plane_alpha(double o, double h, int p, double S, double inv)
 {
 #pragma clang fp contract(off)
-    return (o + (double)p * h - S) * inv;
+    return (plane_coord(o, h, p) - S) * inv;
 }
 
 __device__ __forceinline__ double sub_pos(double c0, double hk, int g)
@@ -310,6 +323,170 @@ __global__ void __launch_bounds__(256) line_back_kernel(DevGeom G, LineCfg C, co
     for (int b = 0; b < NBAT; ++b) x[(size_t)(b0 + b) * nvox + out] = T(acc[b]);
 }
 
+// 3D adjoint.  A pass clips, for VB = blockDim / kLineEntries views at once,
+// up to kLineEntries sub-line columns of each view's shadow (one thread each)
+// into LDS; then every lane adds its voxel's pieces for those entries.
+// LDS: sub-row table v, 1/v (C.vtab) | per-view meta | entries (per sub-line
+// column: the column's alpha interval [A0, A1], its inverses, the
+// direction's x and y, the detector column).
+struct LineMeta {
+    int g0, n;  // first sub-line column of the column's shadow and their count
+};
+
+template <typename T, int NBAT>
+__global__ void __launch_bounds__(256) line_back3d_kernel(DevGeom G, LineCfg C, const T *__restrict__ y,
+                                                           T *__restrict__ x, int b0)
+{
+    extern __shared__ __align__(16) unsigned char lsm[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int VB = nthr / kLineEntries;  // views per pass
+    const int nsu = G.nu * C.k, nsv = G.nv * C.k;
+    double *vt = reinterpret_cast<double *>(lsm);
+    double *vinv = vt + (C.vtab ? nsv : 0);
+    double *eA0 = vinv + (C.vtab ? nsv : 0);  // [VB][kLineEntries] each
+    double *eA1 = eA0 + nthr, *eiA0 = eA1 + nthr, *eiA1 = eiA0 + nthr, *edx = eiA1 + nthr, *edy = edx + nthr;
+    int *em = reinterpret_cast<int *>(edy + nthr);
+    LineMeta *meta = reinterpret_cast<LineMeta *>(em + nthr);  // [VB]
+
+    const int col = xcd_remap(blockIdx.x, gridDim.x);
+    const int ix = col % G.nx, iy = col / G.nx;
+    const double X0 = G.x0 + (double)ix * G.a, X1 = G.x0 + (double)(ix + 1) * G.a;
+    const double Y0 = G.y0 + (double)iy * G.b, Y1 = G.y0 + (double)(iy + 1) * G.b;
+    const int64_t nel = (int64_t)G.n_p * G.nv * G.nu;
+    const size_t nvox = (size_t)G.nx * G.ny * G.nz;
+    const double inv_dvk = 1.0 / C.dv_k, inv_k = 1.0 / C.k;
+    if (C.vtab) {
+        for (int g = tid; g < nsv; g += nthr) {
+            const double v = sub_pos(G.v0, C.dv_k, g);
+            vt[g] = v;
+            vinv[g] = v != 0.0 ? 1.0 / v : 0.0;
+        }
+    }
+    // this thread's slot in the clip phase
+    const int cs_v = tid / kLineEntries, cs_i = tid - cs_v * kLineEntries;
+    for (int z0 = 0; z0 < G.nz; z0 += nthr) {
+        const int iz = z0 + tid;
+        const bool act = iz < G.nz;
+        // the voxel's z planes, as plane_alpha forms them (the source is at z = 0)
+        const double Z0 = plane_coord(G.z0, G.c, iz), Z1 = plane_coord(G.z0, G.c, iz + 1);
+        double acc[NBAT];
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) acc[b] = 0.0;
+        for (int vbase = 0; vbase < G.n_p; vbase += VB) {
+            for (int gb = 0;; gb += kLineEntries) {
+                __syncthreads();  // previous entries consumed (and the table written)
+                {
+                    const int view = vbase + cs_v;
+                    double A0 = INFINITY, A1 = -INFINITY, dx = 0.0, dy = 0.0;
+                    int m = 0, n = 0, g0 = 0;
+                    if (view < G.n_p) {
+                        const double2 cs = G.trig[view];
+                        const double cp = cs.x, sp = cs.y;
+                        // the column's shadow (a range only: sub-lines outside it miss)
+                        double umin = INFINITY, umax = -INFINITY;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const double xc = (c & 1) ? X1 : X0, yc = (c & 2) ? Y1 : Y0;
+                            const double l = G.s - (xc * cp + yc * sp), t = yc * cp - xc * sp;
+                            const double u = G.D * t / l;
+                            umin = fmin(umin, u);
+                            umax = fmax(umax, u);
+                        }
+                        int g1;
+                        sub_range(umin, umax, G.u0, C.du_k, nsu, g0, g1);
+                        n = g1 >= g0 ? g1 - g0 + 1 : 0;
+                        const int i = gb + cs_i;
+                        if (i < n) {
+                            const int gu = g0 + i;
+                            const double u = sub_pos(G.u0, C.du_k, gu);
+                            sub_dir(G.D, cp, sp, u, dx, dy);
+                            double lx, hx, ly, hy;
+                            if (slab(G.x0, G.a, ix, G.s * cp, dx, lx, hx) &&
+                                slab(G.y0, G.b, iy, G.s * sp, dy, ly, hy)) {
+                                A0 = fmax(0.0, fmax(lx, ly));
+                                A1 = fmin(hx, hy);
+                            }
+                            m = (int)(((double)gu + 0.5) * inv_k);
+                        }
+                    }
+                    eA0[tid] = A0;
+                    eA1[tid] = A1;
+                    eiA0[tid] = 1.0 / A0;
+                    eiA1[tid] = 1.0 / A1;
+                    edx[tid] = dx;
+                    edy[tid] = dy;
+                    em[tid] = m;
+                    if (cs_i == 0) meta[cs_v] = LineMeta{g0, n};
+                }
+                __syncthreads();
+                int nmax = 0;
+                for (int vs = 0; vs < VB; ++vs) {
+                    const int view = vbase + vs;
+                    const int n = meta[vs].n;
+                    nmax = n > nmax ? n : nmax;
+                    const int ne = n - gb < kLineEntries ? n - gb : kLineEntries;
+                    if (!act || ne <= 0) continue;
+                    const T *yv = y + (size_t)view * G.nv * G.nu;
+                    const int base = vs * kLineEntries;
+                    for (int e = base; e < base + ne; ++e) {
+                        const double A0 = eA0[e], A1 = eA1[e];
+                        if (!(A0 < A1)) continue;
+                        const double dx = edx[e], dy = edy[e];
+                        const int m = em[e];
+                        // heights v whose line meets the slab for some alpha in [A0, A1]
+                        // (a 1e-9 sub-row margin covers rounding; the slab test decides)
+                        const double vlo = Z0 >= 0.0 ? Z0 * eiA1[e] : Z0 * eiA0[e];
+                        const double vhi = Z1 >= 0.0 ? Z1 * eiA0[e] : Z1 * eiA1[e];
+                        const int gv0 = (int)fmax(ceil((vlo - G.v0) * inv_dvk - 0.5 - 1e-9), 0.0);
+                        const int gv1 = (int)fmin(floor((vhi - G.v0) * inv_dvk - 0.5 + 1e-9), (double)(nsv - 1));
+                        for (int gv = gv0; gv <= gv1; ++gv) {
+                            double v, iv;
+                            if (C.vtab) {
+                                v = vt[gv];
+                                iv = vinv[gv];
+                            } else {
+                                v = sub_pos(G.v0, C.dv_k, gv);
+                                iv = v != 0.0 ? 1.0 / v : 0.0;
+                            }
+                            double lz, hz;
+                            if (v != 0.0) {
+                                const double a = (Z0 - 0.0) * iv, bq = (Z1 - 0.0) * iv;  // plane_alpha
+                                lz = fmin(a, bq);
+                                hz = fmax(a, bq);
+                            } else {
+                                if (par_cell(G.z0, G.c, 0.0) != (double)iz) continue;
+                                lz = -INFINITY;
+                                hz = INFINITY;
+                            }
+                            const double a0 = fmax(A0, lz), a1 = fmin(A1, hz);
+                            if (!(a0 < a1)) continue;
+                            const double R = C.measure ? 0.0 : line_norm(dx, dy, v);
+                            const double w = piece_weight<3>(C, R, a0, a1);
+                            const int r = (int)(((double)gv + 0.5) * inv_k);  // gv / k: the fraction stays >= 1/(2k)
+                            const size_t el = (size_t)r * G.nu + m;
+#pragma unroll
+                            for (int b = 0; b < NBAT; ++b) acc[b] += w * (double)yv[(size_t)(b0 + b) * nel + el];
+                        }
+                    }
+                }
+                if (gb + kLineEntries >= nmax) break;
+            }
+        }
+        if (act) {
+            const size_t out = ((size_t)iz * G.ny + iy) * G.nx + ix;
+#pragma unroll
+            for (int b = 0; b < NBAT; ++b) x[(size_t)(b0 + b) * nvox + out] = T(acc[b]);
+        }
+    }
+}
+
+static size_t line_back3d_lds(const DevGeom &G, const LineCfg &C, int nthr)
+{
+    const size_t tab = C.vtab ? 2 * sizeof(double) * (size_t)G.nv * C.k : 0;
+    return tab + (size_t)nthr * (6 * sizeof(double) + sizeof(int)) +
+           sizeof(LineMeta) * (size_t)(nthr / kLineEntries);
+}
+
 template <typename T, int DIM>
 static hipError_t line_launch(const DevGeom &G, const LineCfg &C, bool adjoint, const void *in, void *out,
                               int B, hipStream_t st)
@@ -318,7 +495,19 @@ static hipError_t line_launch(const DevGeom &G, const LineCfg &C, bool adjoint, 
     const unsigned blocks = (unsigned)((n + 255) / 256);
     for (int b0 = 0; b0 < B;) {
         const int nb = B - b0 >= 4 ? 4 : 1;
-        if (adjoint) {
+        if (adjoint && DIM == 3) {
+            // one workgroup per voxel column, lanes along z
+            const int zt = G.nz < 256 ? G.nz : 256;
+            const int nt = 64 * ((zt + 63) / 64);
+            const size_t lds = line_back3d_lds(G, C, nt);
+            const unsigned cols = (unsigned)((int64_t)G.nx * G.ny);
+            if (nb == 4)
+                hipLaunchKernelGGL((line_back3d_kernel<T, 4>), dim3(cols), dim3(nt), lds, st, G, C,
+                                   (const T *)in, (T *)out, b0);
+            else
+                hipLaunchKernelGGL((line_back3d_kernel<T, 1>), dim3(cols), dim3(nt), lds, st, G, C,
+                                   (const T *)in, (T *)out, b0);
+        } else if (adjoint) {
             if (nb == 4)
                 hipLaunchKernelGGL((line_back_kernel<T, DIM, 4>), dim3(blocks), dim3(256), 0, st, G, C,
                                    (const T *)in, (T *)out, b0);
@@ -366,6 +555,7 @@ sm_status line_apply(const sm_plan *p, int32_t k, sm_line_weight weight, const v
     C.dv_k = G.dv / k;
     C.wl = G.dim == 3 ? 1.0 / ((double)k * k) : 1.0 / k;
     C.wm = G.dim == 3 ? G.du * G.dv * G.D / (3.0 * k * k) : G.du * G.D / (2.0 * k);
+    C.vtab = (int64_t)G.nv * k <= smk::kLineVtab;
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = p->prec == SM_FP64;
     hipError_t e;

@@ -206,6 +206,13 @@ SolveWs solve_layout(const sm_plan *p, sm_solver kind, int B, int64_t proj)
     return L;
 }
 
+// The operator pair a solver applies: the consistent W of sm_forward/sm_back
+// (line_k = 0) or the line-based model of sm_line_forward/sm_line_back.
+struct Op {
+    int line_k;
+    sm_line_weight weight;
+};
+
 struct Ctx {
     const sm_plan *p;
     hipStream_t st;
@@ -214,6 +221,7 @@ struct Ctx {
     void *ws;
     int64_t proj;
     double *S, *part;
+    Op op;
 };
 
 dim3 vec_grid(int64_t n, int B)
@@ -293,18 +301,25 @@ hipError_t record(Ctx &c, double *hist, int row, int slot)
 
 sm_status fwd(Ctx &c, const void *x, void *y)
 {
+    if (c.op.line_k > 0) return sm_line_forward(c.p, c.op.line_k, c.op.weight, x, y, c.B, (void *)c.st);
     return sm_forward(c.p, x, y, c.B, c.ws, c.proj, (void *)c.st);
 }
 
 sm_status bwd(Ctx &c, const void *y, void *x)
 {
+    if (c.op.line_k > 0) return sm_line_back(c.p, c.op.line_k, c.op.weight, y, x, c.B, (void *)c.st);
     return sm_back(c.p, y, x, c.B, c.ws, c.proj, (void *)c.st);
 }
 
 sm_status start(const sm_plan *p, sm_solver kind, int32_t batch, void *ws, int64_t ws_bytes,
-                void *stream, Ctx &c, SolveWs &L)
+                void *stream, Op op, Ctx &c, SolveWs &L)
 {
     if (!p) return set_error(SM_EINVAL, "plan is NULL");
+    if (op.line_k < 0 || op.line_k > SM_LINE_MAX_K)
+        return set_error(SM_EINVAL, "k must be in [1, %d]", SM_LINE_MAX_K);
+    if (op.weight != SM_LINE_LENGTH && op.weight != SM_LINE_MEASURE)
+        return set_error(SM_EINVAL, "bad line weighting");
+    c.op = op;
     if (batch < 1 || batch > 64) return set_error(SM_EINVAL, "batch must be in [1, 64]");
     sm_status s = check_plan_device(p);
     if (s != SM_OK) return s;
@@ -355,14 +370,18 @@ sm_status sm_solver_workspace_size(const sm_plan *p, sm_solver kind, int32_t bat
     return SM_OK;
 }
 
-sm_status sm_power_norm(const sm_plan *p, const void *v0, int32_t iters, double *norm_dev,
+}  // extern "C"
+
+namespace {
+
+sm_status power_norm_op(const sm_plan *p, Op op, const void *v0, int32_t iters, double *norm_dev,
                         void *ws, int64_t ws_bytes, void *stream)
 {
     if (!v0 || !norm_dev) return set_error(SM_EINVAL, "v0 and norm_dev are required");
     if (iters < 1) return set_error(SM_EINVAL, "iters must be >= 1");
     Ctx c;
     SolveWs L;
-    SM_TRYS(start(p, SM_SOLVER_POWER, 1, ws, ws_bytes, stream, c, L));
+    SM_TRYS(start(p, SM_SOLVER_POWER, 1, ws, ws_bytes, stream, op, c, L));
     const int64_t N = p->n_vox, M = p->n_rays;
     char *b = (char *)ws;
     void *u = b + L.off[0], *v = b + L.off[1], *w = b + L.off[2];
@@ -382,6 +401,23 @@ sm_status sm_power_norm(const sm_plan *p, const void *v0, int32_t iters, double 
     return SM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+sm_status sm_power_norm(const sm_plan *p, const void *v0, int32_t iters, double *norm_dev,
+                        void *ws, int64_t ws_bytes, void *stream)
+{
+    return power_norm_op(p, Op{0, SM_LINE_LENGTH}, v0, iters, norm_dev, ws, ws_bytes, stream);
+}
+
+sm_status sm_line_power_norm(const sm_plan *p, int32_t k, sm_line_weight weight, const void *v0,
+                             int32_t iters, double *norm_dev, void *ws, int64_t ws_bytes, void *stream)
+{
+    if (k < 1) return set_error(SM_EINVAL, "k must be in [1, %d]", SM_LINE_MAX_K);
+    return power_norm_op(p, Op{k, weight}, v0, iters, norm_dev, ws, ws_bytes, stream);
+}
+
 sm_status sm_cgls(const sm_plan *p, const void *y, void *x, int32_t batch, int32_t iters,
                   double lambda, double wscale, double *hist_dev, void *ws, int64_t ws_bytes,
                   void *stream)
@@ -391,7 +427,7 @@ sm_status sm_cgls(const sm_plan *p, const void *y, void *x, int32_t batch, int32
         return set_error(SM_EINVAL, "need iters >= 0, lambda >= 0, wscale > 0");
     Ctx c;
     SolveWs L;
-    SM_TRYS(start(p, SM_SOLVER_CGLS, batch, ws, ws_bytes, stream, c, L));
+    SM_TRYS(start(p, SM_SOLVER_CGLS, batch, ws, ws_bytes, stream, Op{0, SM_LINE_LENGTH}, c, L));
     const int64_t N = p->n_vox, M = p->n_rays;
     const double s2 = wscale * wscale;
     char *b = (char *)ws;
@@ -425,7 +461,11 @@ sm_status sm_cgls(const sm_plan *p, const void *y, void *x, int32_t batch, int32
     return SM_OK;
 }
 
-sm_status sm_nag(const sm_plan *p, const void *y, void *x, int32_t batch, int32_t iters,
+}  // extern "C"
+
+namespace {
+
+sm_status nag_op(const sm_plan *p, Op op, const void *y, void *x, int32_t batch, int32_t iters,
                  double lambda, double wscale, const double *norm_dev, double *hist_dev, void *ws,
                  int64_t ws_bytes, void *stream)
 {
@@ -434,7 +474,7 @@ sm_status sm_nag(const sm_plan *p, const void *y, void *x, int32_t batch, int32_
         return set_error(SM_EINVAL, "need iters >= 0, lambda >= 0, wscale > 0");
     Ctx c;
     SolveWs L;
-    SM_TRYS(start(p, SM_SOLVER_NAG, batch, ws, ws_bytes, stream, c, L));
+    SM_TRYS(start(p, SM_SOLVER_NAG, batch, ws, ws_bytes, stream, op, c, L));
     const int64_t N = p->n_vox, M = p->n_rays;
     char *b = (char *)ws;
     void *res = b + L.off[0], *g = b + L.off[1], *z = b + L.off[2], *xprev = b + L.off[3];
@@ -463,6 +503,27 @@ sm_status sm_nag(const sm_plan *p, const void *y, void *x, int32_t batch, int32_
         t = tn;
     }
     return SM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sm_status sm_nag(const sm_plan *p, const void *y, void *x, int32_t batch, int32_t iters,
+                 double lambda, double wscale, const double *norm_dev, double *hist_dev, void *ws,
+                 int64_t ws_bytes, void *stream)
+{
+    return nag_op(p, Op{0, SM_LINE_LENGTH}, y, x, batch, iters, lambda, wscale, norm_dev, hist_dev, ws,
+                  ws_bytes, stream);
+}
+
+sm_status sm_line_nag(const sm_plan *p, int32_t k, sm_line_weight weight, const void *y, void *x,
+                      int32_t batch, int32_t iters, double lambda, double wscale, const double *norm_dev,
+                      double *hist_dev, void *ws, int64_t ws_bytes, void *stream)
+{
+    if (k < 1) return set_error(SM_EINVAL, "k must be in [1, %d]", SM_LINE_MAX_K);
+    return nag_op(p, Op{k, weight}, y, x, batch, iters, lambda, wscale, norm_dev, hist_dev, ws, ws_bytes,
+                  stream);
 }
 
 }  // extern "C"

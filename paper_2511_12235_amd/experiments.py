@@ -29,6 +29,17 @@ The MSE the paper prints for its area/volume-based reconstructions
 (Sec. IV, figures "2D-checkerboard" and "3D-checkerboard-slices") are
 listed beside ours as context only: the noise draw, the pixel size and the
 solver details are not fully given.
+
+``complexity`` is the paper's 2D complexity comparison (Sec. IV, figure
+"complexity"): a 40 x 40 phantom, data p = W u / ||W|| + noise (sigma =
+1e-4) from the consistent (area) model, reconstructed by NAG with lambda in
+{1e-5, 1e-4} using the area matrix and the line-based model with k = 1, 2,
+4, ... lines per detector element ("length": averaged path lengths, the
+paper's comparison; "measure": the midpoint rule of the element's area),
+each operator normalised by its own spectral norm.  Reported per run: the
+MSE to the phantom at the paper's stopping rule, the iterations, the solve
+time and the time of one forward + adjoint pair.  The paper's phantom is a
+Shepp-Logan head; a seeded random-ellipse phantom of the same size stands in.
 """
 from __future__ import annotations
 
@@ -114,6 +125,65 @@ def run(dim: int, n: int, reading: str = "fov", precision: str = "fp64", seed: i
             "x": xs}
 
 
+COMPLEXITY_LAMS = (1e-5, 1e-4)
+COMPLEXITY_KS = (1, 2, 4, 8, 16, 32, 64)
+
+
+def complexity_phantom(g, seed: int = 0) -> np.ndarray:
+    """Seeded ellipse phantom scaled to [0, 1] (stand-in for Shepp-Logan)."""
+    u = wl.ellipse_phantom(g, 8, seed=seed)
+    u = u - u.min()
+    return u / max(float(u.max()), 1e-300)
+
+
+def _time_pair(A, x, y, line, reps: int = 20) -> float:
+    """Milliseconds of one forward + adjoint pair (events on the current stream)."""
+    f = (lambda: (A.forward(x), A.back(y))) if line is None else \
+        (lambda: (A.line_forward(x, line[0], line[1]), A.line_back(y, line[0], line[1])))
+    f()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        f()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def complexity(n: int = 40, reading: str = "fov", lams=COMPLEXITY_LAMS, ks=COMPLEXITY_KS,
+               weights=("length", "measure"), seed: int = 0, device: Optional[str] = None):
+    """The complexity comparison; yields one dict per (model, k, lambda)."""
+    import time
+    dev = torch.device(device or "cuda:0")
+    g = geometry(2, n, reading)
+    A = SystemMatrix(g, "fp64", device=dev)
+    u = complexity_phantom(g, seed)
+    ut = torch.from_numpy(u).to(dev, torch.float64)
+    v0 = torch.from_numpy(start_vector(g, seed + 1)).to(dev, torch.float64)
+    nv = float(A.power_norm(v0, POWER_ITERS).item())
+    p = A.forward(ut) / nv + torch.from_numpy(noise(g, seed + 2)).to(dev, torch.float64)
+    models = [("area", 0, None)] + [("line-" + w, k, (k, w)) for w in weights for k in ks]
+    ysino = torch.ones(g.sino_shape, dtype=torch.float64, device=dev)
+    for name, k, line in models:
+        norm = A.power_norm(v0, POWER_ITERS, line=line)
+        nm = float(norm.item())
+        pair_ms = _time_pair(A, ut, ysino, line)
+        for lam in lams:
+            x, hist = A.nag(p, ITERS[2], norm, lam=lam, wscale=1.0 / nm, line=line)
+            h = hist.cpu().numpy()[:, 0]
+            below = np.nonzero(h < STOP)[0]
+            k_stop = int(below[0]) if below.size else ITERS[2]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xs, _ = A.nag(p, k_stop, norm, lam=lam, wscale=1.0 / nm, line=line)
+            torch.cuda.synchronize()
+            solve_s = time.perf_counter() - t0
+            xk = xs.double().cpu().numpy()
+            yield {"model": name, "k": k, "lambda": lam, "norm": nm, "stop_iter": k_stop,
+                   "mse": float(np.mean((xk - u) ** 2)), "solve_ms": 1e3 * solve_s,
+                   "pair_ms": pair_ms}
+
+
 def main(argv=None) -> None:
     import argparse
     ap = argparse.ArgumentParser(description="checkerboard reconstructions of Sec. IV")
@@ -121,7 +191,13 @@ def main(argv=None) -> None:
     ap.add_argument("--sizes", default="16,32,48,64")
     ap.add_argument("--readings", default="fov,unit")
     ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--complexity", action="store_true",
+                    help="run the 2D complexity comparison (area vs line-based) instead")
     args = ap.parse_args(argv)
+    if args.complexity:
+        for r in complexity():
+            print(json.dumps(r), flush=True)
+        return
     for dim in [int(v) for v in args.dims.split(",")]:
         for reading in args.readings.split(","):
             for n in [int(v) for v in args.sizes.split(",")]:

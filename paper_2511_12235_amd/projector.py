@@ -172,9 +172,11 @@ class SystemMatrix:
         return torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
 
     def power_norm(self, v0: torch.Tensor, iters: int = 100, out: torch.Tensor | None = None,
-                   ws: torch.Tensor | None = None) -> torch.Tensor:
+                   ws: torch.Tensor | None = None, line=None) -> torch.Tensor:
         """||W||_2 by power iteration from the start volume v0 (sm_power_norm);
-        returns a one-element float64 device tensor (no synchronisation)."""
+        returns a one-element float64 device tensor (no synchronisation).
+        line=(k, weight) iterates the line-based model instead
+        (sm_line_power_norm)."""
         if self._check(v0, self.vol_shape, "v0") != 1 or v0.dim() != 3:
             raise ValueError("v0 must be one volume")
         if out is None:
@@ -182,8 +184,14 @@ class SystemMatrix:
         if ws is None:
             ws = self.solver_workspace(_lib.SM_SOLVER_POWER, 1)
         st = torch.cuda.current_stream(self.device).cuda_stream
-        _lib.check(_lib.lib().sm_power_norm(self._plan, v0.data_ptr(), int(iters), out.data_ptr(),
-                                            ws.data_ptr(), ws.numel(), st), "sm_power_norm")
+        if line is None:
+            _lib.check(_lib.lib().sm_power_norm(self._plan, v0.data_ptr(), int(iters), out.data_ptr(),
+                                                ws.data_ptr(), ws.numel(), st), "sm_power_norm")
+        else:
+            k, weight = line
+            _lib.check(_lib.lib().sm_line_power_norm(self._plan, int(k), self._line_weight(weight),
+                                                     v0.data_ptr(), int(iters), out.data_ptr(),
+                                                     ws.data_ptr(), ws.numel(), st), "sm_line_power_norm")
         return out
 
     def _solve_args(self, y, x0, iters, hist_rows):
@@ -212,19 +220,28 @@ class SystemMatrix:
         return x, hist
 
     def nag(self, y: torch.Tensor, iters: int, norm: torch.Tensor, lam: float = 0.0,
-            wscale: float = 1.0, x0: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+            wscale: float = 1.0, x0: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+            line=None):
         """Nesterov / FISTA for the same objective with step 1/(s^2 norm^2 + lam)
         (sm_nag); norm is a one-element float64 device tensor such as
-        power_norm() returns.  Returns (x, hist), hist[k] = |grad F(z_k)|^2."""
+        power_norm() returns.  Returns (x, hist), hist[k] = |grad F(z_k)|^2.
+        line=(k, weight) solves with the line-based model (sm_line_nag)."""
         B, x, hist = self._solve_args(y, x0, iters, lambda n: max(n, 1))
         if not (isinstance(norm, torch.Tensor) and norm.dtype == torch.float64 and norm.device == self.device):
             raise TypeError("norm must be a float64 tensor on the plan's device")
         if ws is None:
             ws = self.solver_workspace(_lib.SM_SOLVER_NAG, B)
         st = torch.cuda.current_stream(self.device).cuda_stream
-        _lib.check(_lib.lib().sm_nag(self._plan, y.data_ptr(), x.data_ptr(), B, int(iters), float(lam),
-                                     float(wscale), norm.data_ptr(), hist.data_ptr(), ws.data_ptr(),
-                                     ws.numel(), st), "sm_nag")
+        if line is None:
+            _lib.check(_lib.lib().sm_nag(self._plan, y.data_ptr(), x.data_ptr(), B, int(iters), float(lam),
+                                         float(wscale), norm.data_ptr(), hist.data_ptr(), ws.data_ptr(),
+                                         ws.numel(), st), "sm_nag")
+        else:
+            k, weight = line
+            _lib.check(_lib.lib().sm_line_nag(self._plan, int(k), self._line_weight(weight), y.data_ptr(),
+                                              x.data_ptr(), B, int(iters), float(lam), float(wscale),
+                                              norm.data_ptr(), hist.data_ptr(), ws.data_ptr(), ws.numel(),
+                                              st), "sm_line_nag")
         return x, hist[:iters]
 
     # ----------------------------------------------------------------- timing

@@ -12,6 +12,7 @@ import pytest
 import torch
 
 from oracle import lines as LN
+from oracle import solvers as SV
 from paper_2511_12235_amd import workloads as wl
 from paper_2511_12235_amd.projector import SystemMatrix
 
@@ -158,3 +159,25 @@ def test_line_full_size_sampled():
     yw = A.line_forward(_t(x, "fp32"), 1, "measure").double().cpu().numpy()
     lhs, rhs = float(np.vdot(yw, ys)), float(np.vdot(x, xb))
     assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
+
+
+@pytest.mark.parametrize("weight", ["length", "measure"])
+def test_line_solvers_match_oracle(weight):
+    """sm_line_power_norm and sm_line_nag against the oracle's power iteration
+    and NAG run on the oracle's line matrix."""
+    g = GEOMS["fan"]
+    k = 3
+    _say("line solvers", weight)
+    W = _W("fan", k, weight)
+    A = SystemMatrix(g, "fp64", device=DEV)
+    v0 = wl.uniform(g.vol_shape, 21)
+    norm = A.power_norm(_t(v0, "fp64"), 50, line=(k, weight))
+    ref = SV.power_norm(W, v0.ravel(), 50)
+    assert abs(norm.item() - ref) <= 1e-12 * ref
+    u = wl.ellipse_phantom(g, 3, seed=22).ravel()
+    p = (W @ u) / ref + 1e-4 * np.random.default_rng(23).normal(size=g.n_rays)
+    x, hist = A.nag(_t(p.reshape(g.sino_shape), "fp64"), 60, norm, lam=1e-4, wscale=1.0 / ref,
+                    line=(k, weight))
+    x_ref, h_ref = SV.nag(W, p, np.zeros(g.n_vox), 60, ref, lam=1e-4, s=1.0 / ref)
+    assert _rel(x.cpu().numpy(), x_ref) <= 1e-10
+    assert _rel(hist.cpu().numpy()[:, 0], h_ref) <= 1e-8
