@@ -68,6 +68,9 @@ def parse():
                     help="time the stored-W mode beside the matrix-free operators instead")
     ap.add_argument("--cpu-views", type=int, default=0,
                     help="views in the oracle sample (default: one per oracle thread)")
+    ap.add_argument("--keep-records", action="store_true",
+                    help="keep the strip records of every view in the plan (sm_plan_keep_records) "
+                         "instead of rebuilding them in every call")
     ap.add_argument("--line", action="store_true",
                     help="time the line-based model (k lines per element) beside the exact operators")
     ap.add_argument("--line-ks", default="1,2")
@@ -384,6 +387,12 @@ def main():
     A = SystemMatrix(g, args.precision, device=dev)
     dt = A.dtype
     x = torch.from_numpy(wl.ellipse_phantom(g, 10, seed=2)).to(dev, dt)
+    keep_s = None
+    if args.keep_records:  # geometry-only tables, built once before the timed region
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A.keep_records()
+        keep_s = time.perf_counter() - t0
     ws = A.workspace(1)
     y = torch.empty(A.sino_shape, dtype=dt, device=dev)
     xb = torch.empty(A.vol_shape, dtype=dt, device=dev)
@@ -461,7 +470,9 @@ def main():
                    "ms_adjoint": float(np.mean(t_b)) * 1e3, "nnz_count_s": count_s,
                    "wall_s": wall,
                    "kernel_ms": {k: round(v[1] / args.steps, 3) for k, v in kt.items()},
-                   "pct_hbm_roofline_effective": 100.0 * eff_bw / HBM_PEAK_GBS},
+                   "pct_hbm_roofline_effective": 100.0 * eff_bw / HBM_PEAK_GBS,
+                   "records": ("kept in the plan: %.1f GB built once in %.2f s" % (A.record_bytes() / 1e9, keep_s)
+                               if args.keep_records else "rebuilt in every call")},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

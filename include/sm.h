@@ -34,8 +34,9 @@
  *  - sm_forward / sm_back are stream-ordered on the given hipStream_t (NULL =
  *    the default stream); they never allocate, never synchronise and overwrite
  *    their output (no zero-initialisation needed).  A plan is immutable after
- *    creation and may be used concurrently from several host threads and
- *    streams, provided each concurrent call has its own workspace.
+ *    creation, except through sm_plan_keep_records and sm_timing_enable, and
+ *    may be used concurrently from several host threads and streams, provided
+ *    each concurrent call has its own workspace.
  */
 #ifndef SM_H
 #define SM_H
@@ -95,6 +96,23 @@ sm_status sm_plan_destroy(sm_plan *plan);
 /* Problem sizes: number of voxels N and number of measurements M = N_d N_p
  * (Sec. I).  Either output pointer may be NULL. */
 sm_status sm_plan_sizes(const sm_plan *plan, int64_t *n_vox, int64_t *n_rays);
+
+/* Bytes of the strip records of every view (the top-view polygons of
+ * Sec. III-B with their chord tables, built per chunk of views by every 3D
+ * sm_forward / sm_back call); 0 in 2D. */
+sm_status sm_plan_record_bytes(const sm_plan *plan, int64_t *bytes);
+
+/* Keep the strip records of every view in a plan-owned device buffer, so
+ * that sm_forward and sm_back (and the solvers built on them) stop
+ * rebuilding them on every call.  The records depend on the geometry only;
+ * results are bitwise the same with and without the buffer.  Builds the
+ * buffer (sm_plan_record_bytes bytes, allocated on the plan's device) if that
+ * is at most max_bytes, else returns SM_ERANGE and changes nothing;
+ * max_bytes = 0 releases it.  Either way synchronises `hip_stream` (and, on
+ * release, the device).  While the buffer is held, sm_workspace_size leaves
+ * out the records.  This call changes the plan: it must not run concurrently
+ * with any other call on the plan.  No-op in 2D. */
+sm_status sm_plan_keep_records(sm_plan *plan, int64_t max_bytes, void *hip_stream);
 
 /* Device workspace bytes that sm_forward / sm_back need for `batch` volumes
  * (0 in 2D).  In 3D it holds the strip records of one chunk of views (the

@@ -17,6 +17,7 @@ SM_OK, SM_EINVAL, SM_ENOMEM, SM_EDEVICE, SM_EUNSUPPORTED, SM_ERANGE = range(6)
 SM_FP32, SM_FP64 = 0, 1
 
 EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_workspace_size",
+            "sm_plan_record_bytes", "sm_plan_keep_records",
             "sm_forward", "sm_back", "sm_line_forward", "sm_line_back",
             "sm_weights_csr", "sm_stored_count", "sm_stored_fill", "sm_stored_apply",
             "sm_footprints", "sm_solver_workspace_size", "sm_power_norm",
@@ -79,6 +80,10 @@ def lib():
         L.sm_plan_sizes.restype = C.c_int
         L.sm_plan_sizes.argtypes = [vp, i64p, i64p]
         L.sm_workspace_size.restype = C.c_int
+        L.sm_plan_record_bytes.restype = C.c_int
+        L.sm_plan_record_bytes.argtypes = [vp, i64p]
+        L.sm_plan_keep_records.restype = C.c_int
+        L.sm_plan_keep_records.argtypes = [vp, C.c_int64, vp]
         L.sm_workspace_size.argtypes = [vp, C.c_int32, i64p]
         L.sm_forward.restype = C.c_int
         L.sm_forward.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_int64, vp]

@@ -345,9 +345,61 @@ sm_status sm_plan_destroy(sm_plan *p)
     if (!p) return SM_OK;
     timing_release(p->tm);
     delete p->tm;
+    hipFree(p->rec_cache);
     hipFree(p->d_trig);
     hipFree(p->d_tau);
     delete p;
+    return SM_OK;
+}
+
+static int64_t record_bytes(const sm_plan *p);
+
+sm_status sm_plan_record_bytes(const sm_plan *p, int64_t *bytes)
+{
+    if (!p) return fail(SM_EINVAL, "plan is NULL");
+    if (!bytes) return fail(SM_EINVAL, "bytes is NULL");
+    *bytes = record_bytes(p);
+    return SM_OK;
+}
+
+sm_status sm_plan_keep_records(sm_plan *p, int64_t max_bytes, void *stream)
+{
+    if (!p) return fail(SM_EINVAL, "plan is NULL");
+    if (max_bytes < 0) return fail(SM_EINVAL, "max_bytes must be >= 0");
+    sm_status s = check_device(p);
+    if (s != SM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (max_bytes == 0 || p->G.dim != 3) {  // release (nothing is kept in 2D)
+        if (p->rec_cache) {
+            hipError_t e = hipStreamSynchronize(st);
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "sm_plan_keep_records");
+            hipFree(p->rec_cache);
+            p->rec_cache = nullptr;
+        }
+        return SM_OK;
+    }
+    if (p->rec_cache) return SM_OK;
+    const int64_t total = record_bytes(p);
+    if (total > max_bytes)
+        return fail(SM_ERANGE, "the records need %lld bytes, %lld allowed", (long long)total,
+                    (long long)max_bytes);
+    void *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, (size_t)total);
+    if (e != hipSuccess) return fail(SM_ENOMEM, "record buffer of %lld bytes: %s", (long long)total,
+                                     hipGetErrorString(e));
+    const smk::RecLayout &RL = p->RL;
+    const bool f64 = p->prec == SM_FP64;
+    for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
+        const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
+        e = smk::launch_records(p->G, RL, f64, v0, nvc, (char *)buf + (int64_t)(v0 / RL.views) * RL.data_off, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        hipFree(buf);
+        return hip_fail(e, "sm_plan_keep_records");
+    }
+    p->rec_cache = buf;
     return SM_OK;
 }
 
@@ -368,7 +420,23 @@ static int64_t workspace_bytes(const sm_plan *p, int64_t batch)
     const int64_t fwd = smk::align256(npix * batch * (int64_t)(p->G.nz + 1) * (int64_t)sizeof(double)) +
                         smk::align256(batch * (int64_t)sizeof(unsigned));
     const int64_t adj = (int64_t)p->L.back_groups * npix * batch * p->G.nz * es;
-    return p->RL.data_off + (fwd > adj ? fwd : adj);
+    // the records of one chunk precede the volume buffer unless the plan keeps them
+    return (p->rec_cache ? 0 : p->RL.data_off) + (fwd > adj ? fwd : adj);
+}
+
+// Records of the chunk starting at view v0: the plan's copy, or the workspace
+// (then rebuilt by the caller before use).
+static void *chunk_records(const sm_plan *p, void *ws, int v0)
+{
+    if (!p->rec_cache) return ws;
+    return (char *)p->rec_cache + (int64_t)(v0 / p->RL.views) * p->RL.data_off;
+}
+
+static int64_t record_bytes(const sm_plan *p)
+{
+    if (p->G.dim != 3) return 0;
+    const int64_t chunks = (p->G.n_p + p->RL.views - 1) / p->RL.views;
+    return chunks * p->RL.data_off;
 }
 
 sm_status sm_workspace_size(const sm_plan *p, int32_t batch, int64_t *bytes)
@@ -410,7 +478,7 @@ sm_status sm_forward(const sm_plan *p, const void *x, void *y, int32_t batch, vo
         tm_end(p, q, st);
     } else {
         const smk::RecLayout &RL = p->RL;
-        double *P = (double *)((char *)ws + RL.data_off);
+        double *P = (double *)((char *)ws + (p->rec_cache ? 0 : RL.data_off));
         const int64_t npix = (int64_t)p->G.nx * p->G.ny;
         unsigned *xmax = (unsigned *)((char *)P + smk::align256(npix * batch * (int64_t)(p->G.nz + 1) *
                                                                 (int64_t)sizeof(double)));
@@ -419,12 +487,15 @@ sm_status sm_forward(const sm_plan *p, const void *x, void *y, int32_t batch, vo
         tm_end(p, q, st);
         for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
             const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
-            q = tm_begin(p, SM_KERNEL_RECORDS, st);
-            e = smk::launch_records(p->G, RL, f64, v0, nvc, ws, st);
-            tm_end(p, q, st);
-            if (e != hipSuccess) break;
+            void *rws = chunk_records(p, ws, v0);
+            if (!p->rec_cache) {
+                q = tm_begin(p, SM_KERNEL_RECORDS, st);
+                e = smk::launch_records(p->G, RL, f64, v0, nvc, rws, st);
+                tm_end(p, q, st);
+                if (e != hipSuccess) break;
+            }
             q = tm_begin(p, SM_KERNEL_FORWARD, st);
-            e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, ws, P, xmax, y, batch, st);
+            e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, rws, P, xmax, y, batch, st);
             tm_end(p, q, st);
         }
     }
@@ -446,16 +517,19 @@ sm_status sm_back(const sm_plan *p, const void *y, void *x, int32_t batch, void 
         tm_end(p, q, st);
     } else {
         const smk::RecLayout &RL = p->RL;
-        void *xt = (char *)ws + RL.data_off;
+        void *xt = (char *)ws + (p->rec_cache ? 0 : RL.data_off);
         e = hipSuccess;
         for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
             const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
-            q = tm_begin(p, SM_KERNEL_RECORDS, st);
-            e = smk::launch_records(p->G, RL, f64, v0, nvc, ws, st);
-            tm_end(p, q, st);
-            if (e != hipSuccess) break;
+            void *rws = chunk_records(p, ws, v0);
+            if (!p->rec_cache) {
+                q = tm_begin(p, SM_KERNEL_RECORDS, st);
+                e = smk::launch_records(p->G, RL, f64, v0, nvc, rws, st);
+                tm_end(p, q, st);
+                if (e != hipSuccess) break;
+            }
             q = tm_begin(p, SM_KERNEL_ADJOINT, st);
-            e = smk::launch_back3d(p->G, p->L, RL, f64, v0, nvc, ws, y, xt, batch, v0 == 0, st);
+            e = smk::launch_back3d(p->G, p->L, RL, f64, v0, nvc, rws, y, xt, batch, v0 == 0, st);
             tm_end(p, q, st);
         }
         if (e == hipSuccess) {

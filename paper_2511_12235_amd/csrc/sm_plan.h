@@ -28,6 +28,9 @@ struct sm_plan {
     double *d_tau;
     int64_t n_vox, n_rays;
     SmTiming *tm;
+    // strip records of every view chunk, kept on the device between calls
+    // (sm_plan_keep_records); chunk c at rec_cache + c * RL.data_off
+    void *rec_cache = nullptr;
 };
 
 namespace smk {

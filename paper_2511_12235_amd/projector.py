@@ -81,6 +81,21 @@ class SystemMatrix:
             return t.shape[0]
         raise ValueError("%s has shape %s, expected %s or (B, *%s)" % (name, tuple(t.shape), shape, shape))
 
+    def record_bytes(self) -> int:
+        """Bytes of the strip records of every view (sm_plan_record_bytes)."""
+        n = C.c_int64()
+        _lib.check(_lib.lib().sm_plan_record_bytes(self._plan, C.byref(n)), "sm_plan_record_bytes")
+        return n.value
+
+    def keep_records(self, max_bytes: int | None = None) -> None:
+        """Keep the strip records of every view on the device between calls
+        (sm_plan_keep_records); max_bytes = 0 releases them.  Workspaces sized
+        before this call stay large enough."""
+        n = self.record_bytes() if max_bytes is None else int(max_bytes)
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.lib().sm_plan_keep_records(self._plan, n, st), "sm_plan_keep_records")
+
     def workspace_bytes(self, batch: int = 1) -> int:
         n = C.c_int64()
         _lib.check(_lib.lib().sm_workspace_size(self._plan, int(batch), C.byref(n)), "sm_workspace_size")

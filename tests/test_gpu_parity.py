@@ -173,6 +173,36 @@ def test_fp32_forward_magnitudes(name, oracle_mats):
     assert np.isnan(yn[1]).all()
 
 
+@pytest.mark.parametrize("name", ["cone_small", "cone_aniso_offset", "cone_many_rows"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_kept_records_bitwise(name, prec):
+    """sm_plan_keep_records: the same bits with the records kept in the plan
+    as with the records rebuilt per call, for single and batched calls;
+    a budget below the record size is refused and changes nothing; the
+    workspace shrinks by the records while they are kept."""
+    g = GEOMS[name]
+    _say("kept records", name, prec)
+    A = SystemMatrix(g, prec, device=DEV)
+    X = np.stack([wl.ellipse_phantom(g, 4, seed=50 + i) for i in range(3)])
+    Y = np.stack([wl.uniform(g.sino_shape, 60 + i) for i in range(3)])
+    Xt, Yt = _t(X, prec), _t(Y, prec)
+    ref = (A.forward(Xt[0]), A.back(Yt[0]), A.forward(Xt), A.back(Yt))
+    ws_before = A.workspace_bytes(3)
+    nbytes = A.record_bytes()
+    assert nbytes > 0
+    with pytest.raises(RuntimeError):
+        A.keep_records(nbytes - 1)
+    assert A.workspace_bytes(3) == ws_before
+    A.keep_records()
+    assert A.workspace_bytes(3) < ws_before
+    got = (A.forward(Xt[0]), A.back(Yt[0]), A.forward(Xt), A.back(Yt))
+    for a, b in zip(got, ref):
+        assert torch.equal(a, b)
+    A.keep_records(0)
+    assert A.workspace_bytes(3) == ws_before
+    assert torch.equal(A.forward(Xt[0]), ref[0])
+
+
 def test_deterministic_repeat():
     g = GEOMS["cone_small"]
     _say("determinism")
