@@ -5,6 +5,9 @@ kind "cg" runs CGLS for a fixed number of iterations on a sinogram.  Inputs
 are resident on the device when a request arrives.  The server
 
 * keeps one plan per geometry (plans are immutable and shared by streams);
+  with a record budget, a new plan also keeps its strip records on the
+  device (sm_plan_keep_records) while the budget lasts, so that its calls
+  skip rebuilding them and its workspace shrinks by them;
 * owns a few HIP streams ("slots"); a waiting request is admitted as soon
   as a slot is free and its device footprint fits the HBM budget next to the
   requests already running (first come, first served);
@@ -67,9 +70,11 @@ def percentile(v: Sequence[float], q: float) -> float:
 
 class Server:
     def __init__(self, device=None, hbm_budget: int = 2 << 30, slots: int = 4, max_batch: int = 8,
-                 precision: str = "fp32", keep_results: bool = False):
+                 precision: str = "fp32", keep_results: bool = False, record_budget: int = 0):
         self.device = torch.device(device or "cuda:0")
         self.budget = int(hbm_budget)
+        self.record_budget = int(record_budget)  # HBM for kept records, outside the request budget
+        self.record_used = 0
         self.max_batch = int(max_batch)
         self.precision = precision
         self.keep_results = keep_results
@@ -80,7 +85,12 @@ class Server:
     # ------------------------------------------------------------------ plans
     def plan(self, key: str, geometry) -> SystemMatrix:
         if key not in self.plans:
-            self.plans[key] = SystemMatrix(geometry, self.precision, device=self.device)
+            A = SystemMatrix(geometry, self.precision, device=self.device)
+            nb = A.record_bytes()
+            if 0 < nb <= self.record_budget - self.record_used:
+                A.keep_records(nb)
+                self.record_used += nb
+            self.plans[key] = A
         return self.plans[key]
 
     def footprint(self, r: Request, batch: int) -> int:
@@ -297,11 +307,12 @@ def make_requests(n: int, rate: float, seed: int, device, mix=MIX, iters: int = 
     return out
 
 
-def service_times(device, mix=MIX, views=(90, 180, 360), iters: int = 10, precision: str = "fp32") -> dict:
+def service_times(device, mix=MIX, views=(90, 180, 360), iters: int = 10, precision: str = "fp32",
+                  record_budget: int = 0) -> dict:
     """Time one request of every (geometry, kind, views) type alone (after a
     warm-up call): the per-type service times the mix weights are set from."""
     from . import workloads as wl
-    srv = Server(device, precision=precision)
+    srv = Server(device, precision=precision, record_budget=record_budget)
     out = {}
     for name, kind, _ in mix:
         for n_p in ((360,) if name.startswith("2d") else views):
@@ -341,23 +352,27 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--budget-gib", type=float, default=2.0)
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--record-budget-gib", type=float, default=0.0,
+                    help="HBM for strip records kept in the plans (outside the request budget)")
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--service-times", action="store_true")
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
+    rb = int(args.record_budget_gib * (1 << 30))
     if args.service_times:
-        t = service_times(dev)
+        t = service_times(dev, record_budget=rb)
         print(json.dumps({"service_s": t, "offered_load_at_rate": offered_load(t, args.rate),
                           "rate": args.rate}), flush=True)
         return
     res = {"rate": args.rate, "budget_gib": args.budget_gib, "slots": args.slots,
-           "mix": [list(m) for m in MIX]}
-    srv = Server(dev, hbm_budget=int(args.budget_gib * (1 << 30)), slots=args.slots)
+           "record_budget_gib": args.record_budget_gib, "mix": [list(m) for m in MIX]}
+    srv = Server(dev, hbm_budget=int(args.budget_gib * (1 << 30)), slots=args.slots, record_budget=rb)
     reqs = make_requests(args.requests, args.rate, args.seed, dev)
     srv.prepare(reqs)
     srv.run(reqs, progress=100)
     res["continuous"] = summarize(reqs)
     res["stats"] = dict(srv.stats)
+    res["stats"]["records_kept_bytes"] = srv.record_used
     seq = make_requests(args.requests, args.rate, args.seed, dev)
     srv.run_sequential(seq, progress=100)
     res["sequential"] = summarize(seq)

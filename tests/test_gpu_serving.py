@@ -56,3 +56,21 @@ def test_results_equal_alone_and_in_the_mix():
     assert st["max_concurrent"] >= 2
     assert st["batched"] >= 1
     assert all(r.t_done >= r.arrival for r in reqs)
+
+
+def test_kept_records_change_no_result():
+    """Plans that keep their strip records (record budget) serve the same bits."""
+    print("[case] serving kept records", flush=True)
+    reqs = serve.make_requests(16, 500.0, 5, torch.device(DEV), mix=MIX, iters=4,
+                               geometry=tiny_geometry, views=(30, 60))
+    plain = serve.Server(DEV, keep_results=True)
+    plain.prepare(reqs)
+    plain.run_sequential(reqs)
+    kept = serve.Server(DEV, keep_results=True, record_budget=1 << 34)
+    again = [dataclasses.replace(r, result=None) for r in reqs]
+    kept.prepare(again)
+    kept.run(again)
+    assert kept.record_used > 0
+    assert kept.record_used == sum(A.record_bytes() for A in kept.plans.values())
+    for a, b in zip(reqs, again):
+        assert torch.equal(a.result, b.result), (a.rid, a.key, a.kind)
