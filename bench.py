@@ -68,6 +68,8 @@ def parse():
                     help="time the stored-W mode beside the matrix-free operators instead")
     ap.add_argument("--cpu-views", type=int, default=0,
                     help="views in the oracle sample (default: one per oracle thread)")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="volumes per call (the weights are evaluated once for all of them)")
     ap.add_argument("--keep-records", action="store_true",
                     help="keep the strip records of every view in the plan (sm_plan_keep_records) "
                          "instead of rebuilding them in every call")
@@ -386,16 +388,21 @@ def main():
     dev = torch.device("cuda:0")
     A = SystemMatrix(g, args.precision, device=dev)
     dt = A.dtype
+    B = max(int(args.batch), 1)
     x = torch.from_numpy(wl.ellipse_phantom(g, 10, seed=2)).to(dev, dt)
+    if B > 1:
+        x = torch.stack([x] + [torch.from_numpy(wl.ellipse_phantom(g, 10, seed=2 + i)).to(dev, dt)
+                               for i in range(1, B)])
     keep_s = None
     if args.keep_records:  # geometry-only tables, built once before the timed region
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         A.keep_records()
         keep_s = time.perf_counter() - t0
-    ws = A.workspace(1)
-    y = torch.empty(A.sino_shape, dtype=dt, device=dev)
-    xb = torch.empty(A.vol_shape, dtype=dt, device=dev)
+    ws = A.workspace(B)
+    lead = (B,) if B > 1 else ()
+    y = torch.empty(lead + A.sino_shape, dtype=dt, device=dev)
+    xb = torch.empty(lead + A.vol_shape, dtype=dt, device=dev)
 
     # exact number of nonzero pairs (FP64 pattern), counted on the GPU
     nnz = C.c_int64(0)
@@ -436,16 +443,17 @@ def main():
     t_f = np.array([a.elapsed_time(b) for a, b, _ in ev]) / 1e3
     t_b = np.array([b.elapsed_time(c) for _, b, c in ev]) / 1e3
     step = t_f + t_b
-    value = 2.0 * nnz / float(np.mean(step))
+    value = 2.0 * nnz * B / float(np.mean(step))
     eff_bw = value * 8.0 / 1e9  # GB/s a stored FP32+int32 CSR matrix would stream
 
     # dominant kernel: largest summed launch time in the timed region
     dom = max(("forward", "adjoint", "records", "prefix", "transpose"), key=lambda k: kt[k][1])
     launches, ms = kt[dom]
     ms_launch = ms / max(launches, 1)
-    pairs_per_launch = nnz * args.steps / max(launches, 1) if dom in ("forward", "adjoint") else 0.0
+    pairs_per_launch = nnz * B * args.steps / max(launches, 1) if dom in ("forward", "adjoint") else 0.0
     achieved = FLOP_PER_PAIR * pairs_per_launch / (ms_launch / 1e3) / 1e12 if ms_launch > 0 else 0.0
-    traffic = traffic_per_launch(args.config, args.precision, KERNEL_SYMBOL[dom])
+    # the counter summaries were taken on single-volume launches
+    traffic = traffic_per_launch(args.config, args.precision, KERNEL_SYMBOL[dom]) if B == 1 else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic,
                 "kernel": KERNEL_SYMBOL[dom], "ms_per_launch": ms_launch,
@@ -465,7 +473,7 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "cone-beam %d^3 voxels, %d views, %dx%d detector, forward + adjoint"
-                               % (g.nx, g.n_p, g.det_ny, g.det_nz),
+                               % (g.nx, g.n_p, g.det_ny, g.det_nz) + (", %d volumes per call" % B if B > 1 else ""),
                    "nnz_pairs": nnz, "ms_forward": float(np.mean(t_f)) * 1e3,
                    "ms_adjoint": float(np.mean(t_b)) * 1e3, "nnz_count_s": count_s,
                    "wall_s": wall,

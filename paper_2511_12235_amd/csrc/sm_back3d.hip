@@ -229,14 +229,14 @@ static hipError_t launch_back3d_all(const DevGeom &G, const LaunchCfg &L, const 
 {
     const RecPtrs RP = rec_ptrs(RL, ws, sizeof(Rec<T>));
     const size_t bud = (size_t)L.lds_budget;
-    const bool fit8 = back3d_lds<T, 8, 2, 1>(G, L, 3) <= bud;
     const bool fit4 = back3d_lds<T, 4, 2, 2>(G, L, 2) <= bud;
     const bool fit2 = back3d_lds<T, 2, 4, 2>(G, L, 1) <= bud;
     hipError_t e = hipSuccess;
+    // at most four volumes per launch: eight (2 x 1 tiles) measured slower per
+    // volume than two launches of four at 256^3
     for (int b0 = 0; b0 < B && e == hipSuccess;) {
         const int rem = B - b0;
-        if (rem >= 8 && fit8) { e = launch_back3d_t<T, 8, 2, 1>(G, L, RL, 3, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 8; }
-        else if (rem >= 4 && fit4) { e = launch_back3d_t<T, 4, 2, 2>(G, L, RL, 2, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 4; }
+        if (rem >= 4 && fit4) { e = launch_back3d_t<T, 4, 2, 2>(G, L, RL, 2, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 4; }
         else if (rem >= 2 && fit2) { e = launch_back3d_t<T, 2, 4, 2>(G, L, RL, 1, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 2; }
         else { e = launch_back3d_t<T, 1, 4, 4>(G, L, RL, 0, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 1; }
     }

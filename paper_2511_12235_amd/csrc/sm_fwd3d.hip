@@ -414,14 +414,14 @@ static hipError_t launch_fwd3d_all(const DevGeom &G, const LaunchCfg &L, const R
 {
     RecPtrs RP = rec_ptrs(RL, ws, sizeof(Rec<T>));
     const Rec<T> *recs = (const Rec<T> *)RP.recs;
-    const bool fit8 = fwd3d_qcap<T, 8>(L) > 0;
     const bool fit4 = fwd3d_qcap<T, 4>(L) > 0;
     const bool fit2 = fwd3d_qcap<T, 2>(L) > 0;
     hipError_t e = hipSuccess;
+    // at most four volumes per launch: eight measured slower per volume than
+    // two launches of four at 256^3 (register pressure of the eight sums)
     for (int b0 = 0; b0 < B && e == hipSuccess;) {
         const int rem = B - b0;
-        if (rem >= 8 && fit8) { e = launch_fwd3d_t<T, 8>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 8; }
-        else if (rem >= 4 && fit4) { e = launch_fwd3d_t<T, 4>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 4; }
+        if (rem >= 4 && fit4) { e = launch_fwd3d_t<T, 4>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 4; }
         else if (rem >= 2 && fit2) { e = launch_fwd3d_t<T, 2>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 2; }
         else { e = launch_fwd3d_t<T, 1>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 1; }
     }
