@@ -86,8 +86,10 @@ typedef struct sm_plan sm_plan;
  * device (Sec. III-A).  Rejects (SM_EINVAL) non-positive sizes or pitches,
  * dim not in {2, 3}, non-finite values, and any view in which a grid corner
  * has depth l <= 0 (source inside or behind the grid).  Returns
- * SM_EUNSUPPORTED for det_nz > 1024 in 3D.  The plan must be destroyed with
- * sm_plan_destroy on the same device. */
+ * SM_EUNSUPPORTED in 3D for det_nz > 1024 or nz > 1024, and when a
+ * workgroup's LDS staging would exceed 64 KiB: FP64 plans above about 830
+ * detector rows, or a voxel footprint too wide for the adjoint's tile.  The
+ * plan must be destroyed with sm_plan_destroy on the same device. */
 sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan **out);
 
 /* Release the plan and its device tables.  NULL is accepted. */
