@@ -245,14 +245,14 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             plane_extent<T>(tf0, Llo, Lhi, lo, hi);
             int fa, fb;
             face_split<T>(lo, hi, inv_c, z0c, nz, fa, fb);
-            const int f = fa - 1 < 0 ? 0 : (fa - 1 > nz ? nz : fa - 1);
+            const int f = max(fa - 1, 0);  // fa <= nz + 1
             const int je = fb - 1 < nz ? fb - 1 : nz;
             // first voxel not wholly below plane r + 1, as its own lane finds it
             T lo1, hi1;
             plane_extent<T>(tf1, Llo, Lhi, lo1, hi1);
             int fa1, fb1;
             face_split<T>(lo1, hi1, inv_c, z0c, nz, fa1, fb1);
-            const int f1 = fa1 - 1 < 0 ? 0 : (fa1 - 1 > nz ? nz : fa1 - 1);
+            const int f1 = max(fa1 - 1, 0);
             // prefix sums at f and f + 1 serve the linear term
             const int f2 = f + 1 < nz ? f + 1 : nz;
             const T cA = cT * S.A;
