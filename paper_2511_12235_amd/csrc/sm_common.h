@@ -87,8 +87,9 @@ __device__ __forceinline__ const Rec<T> &lds_rec(const unsigned char *base, int 
     return *reinterpret_cast<const Rec<T> *>(base + (size_t)i * lds_rec_stride<T>());
 }
 
-__host__ __device__ inline double dmin_(double a, double b) { return a < b ? a : b; }
-__host__ __device__ inline double dmax_(double a, double b) { return a > b ? a : b; }
+// one v_min_f64 / v_max_f64 each (the inputs are finite)
+__host__ __device__ inline double dmin_(double a, double b) { return fmin(a, b); }
+__host__ __device__ inline double dmax_(double a, double b) { return fmax(a, b); }
 
 // ---------------------------------------------------------------------------
 // strip polygon: pixel rectangle cut by the wedge u_k <= u <= u_{k+1}
