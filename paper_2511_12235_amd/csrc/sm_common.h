@@ -399,16 +399,19 @@ template <typename T>
 __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
 {
     const T lam = -e * inv_tau;
-    const int j = (lam >= S.b1 ? 1 : 0) + (lam >= S.b2 ? 1 : 0) + (lam >= S.b3 ? 1 : 0) +
-                  (lam >= S.b4 ? 1 : 0);
-    const T *r0 = S.tab[j];
-    const T *r1 = S.tab[j + 1];
+    // row offset in bytes: one select per breakpoint, no shifts
+    constexpr int RB = 4 * (int)sizeof(T);
+    const int jo = (lam >= S.b1 ? RB : 0) + (lam >= S.b2 ? RB : 0) + (lam >= S.b3 ? RB : 0) +
+                   (lam >= S.b4 ? RB : 0);
+    const T *r0 = reinterpret_cast<const T *>(reinterpret_cast<const char *>(S.tab) + jo);
+    const T *r1 = r0 + 4;
     const T dA = r0[0], w0 = r0[1];
     const T dB = r1[0], w1 = r1[1], s0 = r1[2], s1 = r1[3];
     const T L = dB - dA;
     T h = dB - lam;
     h = clamp0(h, L);  // L >= 0: breakpoints ascend
-    const T wl = w1 + (w0 - w1) * (L > T(0) ? h * rcp_(L) : T(0));
+    // h <= L, so a zero-length segment gives h = 0 and the guard keeps 0 * inf out
+    const T wl = w1 + (w0 - w1) * (h * rcp_(L > T(1e-30) ? L : T(1e-30)));
     T psi = h * h * (wl * T(1.0 / 6.0) + w1 * T(1.0 / 3.0)) + s1 + h * s0;
     const T below = S.d0 - lam;
     psi += (below > T(0) ? below : T(0)) * S.A;
@@ -524,7 +527,7 @@ __host__ __device__ inline int adj_straddle(int t, int na, int pha, int phb, con
                                             size_t ystride, T &e, T (&dY)[NBAT])
 {
     const bool top = t >= na;
-    const int q = top ? phb + (t - na) : pha + t;
+    const int q = (top ? phb - na : pha) + t;
     e = T(ptau[q] * lc - (top ? zb : za));
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) {
