@@ -129,8 +129,11 @@ __device__ __forceinline__ void fwd_flush_fixed(const DevGeom &G, const unsigned
     wave_sync();
 }
 
+// The single-volume FP32 instance is held to 64 VGPRs (8 waves per SIMD): the
+// extra waves hide the latency of the prefix-sum gathers better than the few
+// registers the limit spills cost; the other instances keep their registers.
 template <typename T, int NBAT>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(NBAT == 1 && sizeof(T) == 4 ? 8 : 1)))
 fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
              const int *__restrict__ soff, const double *__restrict__ P,
              const unsigned *__restrict__ xmax, T *__restrict__ y, int B, int b0, int qcap)
@@ -229,40 +232,73 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             }
         }
         __syncthreads();
+        // software pipeline: the prefix-sum gathers of record e + 1 are issued
+        // before record e is used (indices of an empty record are clamped, so its
+        // loads stay in range and are not used)
+        auto faces = [&](int e, int &fa, int &je, int &f, int &f1, int &f2) {
+            const Rec<T> &R = Rs[c0 + e];
+            const int n = R.n > 0 ? R.n : 1;
+            const double lc = R.lc;
+            const T Llo = T(lc + (double)R.tab[0][0]), Lhi = T(lc + (double)R.tab[n - 1][0]);
+            T lo, hi;
+            plane_extent<T>(tf0, Llo, Lhi, lo, hi);
+            int fb;
+            face_split<T>(lo, hi, inv_c, z0c, nz, fa, fb);
+            f = max(fa - 1, 0);
+            je = fb - 1 < nz ? fb - 1 : nz;
+            T lo1, hi1;
+            plane_extent<T>(tf1, Llo, Lhi, lo1, hi1);
+            int fa1, fb1;
+            face_split<T>(lo1, hi1, inv_c, z0c, nz, fa1, fb1);
+            f1 = max(fa1 - 1, 0);
+            f2 = f + 1 < nz ? f + 1 : nz;
+        };
+        int nfa = 0, nje = 0, nf = 0, nf1 = 0, nf2 = 0;
+        double np0[NBAT], np1[NBAT], npf[NBAT];
+        if (cnt > 0) {
+            faces(0, nfa, nje, nf, nf1, nf2);
+            const int pix = Rs[c0].pix;
+#pragma unroll
+            for (int b = 0; b < NBAT; ++b) {
+                const double *Pn = P + ((size_t)pix * B + b0 + b) * colstride;
+                np0[b] = Pn[nf];
+                np1[b] = Pn[nf2];
+                npf[b] = Pn[nf1];
+            }
+        }
         for (int e = 0; e < cnt; ++e) {
+            const int fa = nfa, je = nje, f = nf;
+            double p0v[NBAT], p1v[NBAT], pfv[NBAT];
+#pragma unroll
+            for (int b = 0; b < NBAT; ++b) {
+                p0v[b] = np0[b];
+                p1v[b] = np1[b];
+                pfv[b] = npf[b];
+            }
+            if (e + 1 < cnt) {
+                faces(e + 1, nfa, nje, nf, nf1, nf2);
+                const int pix = Rs[c0 + e + 1].pix;
+#pragma unroll
+                for (int b = 0; b < NBAT; ++b) {
+                    const double *Pn = P + ((size_t)pix * B + b0 + b) * colstride;
+                    np0[b] = Pn[nf];
+                    np1[b] = Pn[nf2];
+                    npf[b] = Pn[nf1];
+                }
+            }
             const Rec<T> &R = Rs[c0 + e];  // uniform fields through the scalar cache
             const int n = R.n;
             if (n == 0) continue;
             const StripTab<T> S = strip_tab<T>(R.tab, lds_rec<T>(rbuf, e).tab);
             const double lc = R.lc;
-            const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
             const double lbar = lc + (double)R.lbo;
-            const double *Pc[NBAT];
-#pragma unroll
-            for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;
-            // faces: < fa wholly below plane r, fa .. je straddled, beyond above
-            T lo, hi;
-            plane_extent<T>(tf0, Llo, Lhi, lo, hi);
-            int fa, fb;
-            face_split<T>(lo, hi, inv_c, z0c, nz, fa, fb);
-            const int f = max(fa - 1, 0);  // fa <= nz + 1
-            const int je = fb - 1 < nz ? fb - 1 : nz;
-            // first voxel not wholly below plane r + 1, as its own lane finds it
-            T lo1, hi1;
-            plane_extent<T>(tf1, Llo, Lhi, lo1, hi1);
-            int fa1, fb1;
-            face_split<T>(lo1, hi1, inv_c, z0c, nz, fa1, fb1);
-            const int f1 = max(fa1 - 1, 0);
-            // prefix sums at f and f + 1 serve the linear term
-            const int f2 = f + 1 < nz ? f + 1 : nz;
             const T cA = cT * S.A;
             const T Klin = S.A * T(tau0 * lbar - (G.z0 + (double)f * G.c));
             const bool lin = fa >= 1 && fa <= nz;
 #pragma unroll
             for (int b = 0; b < NBAT; ++b) {
-                const double p0 = Pc[b][f], p1 = Pc[b][f2];
-                const T gs = lin ? Klin * T(p1 - p0) : T(0);
-                acc1[b] += cA * T(Pc[b][f1] - p0) - gs;
+                const T gs = lin ? Klin * T(p1v[b] - p0v[b]) : T(0);
+                acc1[b] += cA * T(pfv[b] - p0v[b]) - gs;
                 acc2[b] += gs;
             }
             // queue the straddled faces fa .. je, one ballot round per face
