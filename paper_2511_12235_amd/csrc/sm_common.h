@@ -323,8 +323,12 @@ __host__ __device__ inline T eval_K(const T (*tab)[4], int n, T tau, T inv_tau, 
 // height z a plane is wholly below (K = 0), wholly above (K = the linear
 // integral A (tau lbar - z), lbar the area-weighted mean depth) or straddles
 // it (K from the chord table).  Both walks below only need the split to be
-// consistent: K_cut is exact for a plane anywhere, and a plane put on the
-// wrong side of a face by rounding is off by a volume of rounding size.
+// consistent: K_cut is exact for a sloped plane anywhere, and a plane put on
+// the wrong side of a face by rounding is off by a volume of rounding size.
+// A horizontal plane (tau = 0) spans the single height 0, so both splits put
+// it wholly on one side of every face (a face at height exactly 0 counts as
+// both, with K = 0 either way); only rounding of a face that should sit at
+// 0 can make it straddle, where its K is of rounding size.
 
 // Clamp to [0, top]: one median instruction in FP32 on the device, a min and
 // a max in FP64 (these run once or twice per record and lane).
@@ -372,7 +376,8 @@ __host__ __device__ inline void face_split(T lo, T hi, T inv_c, T z0c, int nz, i
 template <typename T>
 struct StripTab {
     const T (*tab)[4];
-    T d0, A, S1, b1, b2, b3, b4;  // nearest depth, area, first moment, interior breakpoints
+    T d0, A, S1, M1, b1, b2, b3, b4;  // nearest depth, area, first moments about d0 and the
+                                      // column centre, interior breakpoints
 };
 
 template <typename T>
@@ -383,6 +388,7 @@ __host__ __device__ inline StripTab<T> strip_tab(const T (*tab)[4], const T (*ro
     S.d0 = tab[0][0];
     S.A = tab[0][2];
     S.S1 = tab[0][3];
+    S.M1 = S.S1 + S.d0 * S.A;
     S.b1 = tab[1][0];
     S.b2 = tab[2][0];
     S.b3 = tab[3][0];
@@ -390,11 +396,15 @@ __host__ __device__ inline StripTab<T> strip_tab(const T (*tab)[4], const T (*ro
     return S;
 }
 
-// K = integral over P of (e + tau l')_+ dA for any plane (see eval_K).  The
-// segment of the breakpoint table holding lam = -e / tau is found by
+// K = integral over P of (e + tau l')_+ dA for a sloped plane (see eval_K).
+// The segment of the breakpoint table holding lam = -e / tau is found by
 // counting breakpoints; Psi continues linearly below the nearest depth
 // (Psi(lam) = S1 + (d0 - lam) A there) and is zero beyond the farthest, so
-// the result is exact wherever the plane lies.
+// the result is exact wherever the plane lies.  For tau > 0, K = tau Psi(lam).
+// For tau < 0, writing (w)_+ = w + (-w)_+ gives the plane's linear volume
+// e A + tau M1 (M1 = S1 + d0 A, the first moment about the column centre)
+// plus (-tau) Psi(lam), so both signs take |tau| Psi and one select.  A
+// horizontal plane gets 0 (it never straddles a face; see above).
 template <typename T>
 __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
 {
@@ -415,10 +425,8 @@ __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
     T psi = h * h * (wl * T(1.0 / 6.0) + w1 * T(1.0 / 3.0)) + s1 + h * s0;
     const T below = S.d0 - lam;
     psi += (below > T(0) ? below : T(0)) * S.A;
-    const T kp = tau * psi;                                  // tau > 0
-    const T kn = (-tau) * (psi - S.S1 + (lam - S.d0) * S.A);  // tau < 0
-    const T k0 = e > T(0) ? e * S.A : T(0);                   // horizontal plane
-    return tau > T(0) ? kp : (tau < T(0) ? kn : k0);
+    const T kp = fabs(tau) * psi;
+    return tau < T(0) ? kp + (e * S.A + tau * S.M1) : kp;
 }
 
 // Heights of plane tau over the strip [Llo, Lhi] (depths).
