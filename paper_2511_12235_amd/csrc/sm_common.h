@@ -95,10 +95,17 @@ __host__ __device__ inline double dmax_(double a, double b) { return fmax(a, b);
 // strip polygon: pixel rectangle cut by the wedge u_k <= u <= u_{k+1}
 // ---------------------------------------------------------------------------
 // FP64 throughout (the plane/face intersections and every sign decision);
-// the tables are stored in T.  `ws` is scratch for up to 8 vertices.
-template <typename T, typename RecT>
+// the tables are stored in T.  `ws` is scratch for up to 8 vertices: a
+// pointer, or a strided view (LdsVerts) into a workgroup's shared array.
+struct LdsVerts {
+    double2 *p;  // vertex 0 of this thread
+    int stride;  // elements between consecutive vertices
+    __host__ __device__ double2 &operator[](int i) const { return p[i * stride]; }
+};
+
+template <typename T, typename RecT, typename WS>
 __host__ __device__ inline void build_record(const DevGeom &G, double cp, double sp, int ix, int iy,
-                                             int k, RecT &R, double2 *ws)
+                                             int k, RecT &R, WS ws)
 {
     const double xc = G.x0 + ((double)ix + 0.5) * G.a;
     const double yc = G.y0 + ((double)iy + 0.5) * G.b;

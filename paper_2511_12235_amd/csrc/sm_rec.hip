@@ -50,7 +50,7 @@ rec_kernel(DevGeom G, RecLayout RL, int v0, Rec<T> *__restrict__ recs, int *__re
     __shared__ int offs[257];
     __shared__ int jst[256];
     __shared__ int scan_tmp[8];
-    __shared__ double2 wsp[256][8];
+    __shared__ double2 wsp[8][256];  // vertex i of thread t at [i][t]: no bank conflicts
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int vl = lb / G.nu, k = lb - vl * G.nu;
@@ -96,7 +96,7 @@ rec_kernel(DevGeom G, RecLayout RL, int v0, Rec<T> *__restrict__ recs, int *__re
             const int slot = run + e;
             if (slot < RL.cap) {
                 Rec<T> R;
-                build_record<T>(G, cp, sp, ix, iy, k, R, wsp[tid]);
+                build_record<T>(G, cp, sp, ix, iy, k, R, LdsVerts{&wsp[0][tid], 256});
                 R.pix = iy * G.nx + ix;
                 out[slot] = R;
                 if (R.n > 0) {
