@@ -101,29 +101,27 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
         const int pc = kmax - kmin + 1;
         __syncthreads();  // the previous view's patch and records are consumed
         // --- stage y[view][:, kmin..kmax] with zero rows at -1 and nv
-        {
-            const float inv_pc = 1.0f / (float)pc;
-            const int per_b = pc * nv;
-            for (int bb = 0; bb < NBAT; ++bb) {
-                const T *src = y + ((size_t)(b0 + bb) * G.n_p + view) * nv * G.nu;
-                T *dst = patch + (size_t)bb * pcols * rowstride;
-                for (int q = tid; q < per_b; q += nthr) {
-                    const int row = (int)(((float)q + 0.5f) * inv_pc);
-                    const int col = q - row * pc;
-                    dst[col * rowstride + row + 1] = src[(size_t)row * G.nu + kmin + col];
-                }
-                for (int col = tid; col < pc; col += nthr) {
-                    dst[col * rowstride] = T(0);
-                    dst[col * rowstride + nv + 1] = T(0);
-                }
+        // (one thread per detector row: its pc values lie side by side)
+        for (int bb = 0; bb < NBAT; ++bb) {
+            const T *src = y + ((size_t)(b0 + bb) * G.n_p + view) * nv * G.nu + kmin;
+            T *dst = patch + (size_t)bb * pcols * rowstride + 1;
+            for (int row = tid; row < nv; row += nthr) {
+                const T *s = src + (size_t)row * G.nu;
+                T *d = dst + row;
+                for (int col = 0; col < pc; ++col) d[col * rowstride] = s[col];
+            }
+            for (int col = tid; col < pc; col += nthr) {
+                dst[col * rowstride - 1] = T(0);
+                dst[col * rowstride + nv] = T(0);
             }
         }
         // --- stage the strip records of the tile's pixels in slot (p, k - k0(p));
         // a slot without a record gets n = 0
+        const float inv_rspan = 1.0f / (float)rspan;
         for (int q = tid; q < TP * rspan * RCH; q += nthr) {
-            const int p = q / (rspan * RCH);
-            const int rem = q - p * rspan * RCH;
-            const int kk = rem / RCH, ch = rem - kk * RCH;
+            const int pk = q / RCH, ch = q - pk * RCH;            // RCH is a constant
+            const int p = (int)(((float)pk + 0.5f) * inv_rspan);  // exact for pk < 16 rspan, rspan <= 2048
+            const int kk = pk - p * rspan;
             const int ix = ix0 + p % TX, iy = iy0 + p / TX;
             uint4 *dst = reinterpret_cast<uint4 *>(rtab + p * rspan + kk);
             int pos = -1;
