@@ -101,14 +101,24 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
         const int pc = kmax - kmin + 1;
         __syncthreads();  // the previous view's patch and records are consumed
         // --- stage y[view][:, kmin..kmax] with zero rows at -1 and nv
-        // (one thread per detector row: its pc values lie side by side)
+        // (a single volume: one thread per detector row, its pc values side by
+        // side; batches: consecutive threads on consecutive columns)
         for (int bb = 0; bb < NBAT; ++bb) {
             const T *src = y + ((size_t)(b0 + bb) * G.n_p + view) * nv * G.nu + kmin;
             T *dst = patch + (size_t)bb * pcols * rowstride + 1;
-            for (int row = tid; row < nv; row += nthr) {
-                const T *s = src + (size_t)row * G.nu;
-                T *d = dst + row;
-                for (int col = 0; col < pc; ++col) d[col * rowstride] = s[col];
+            if constexpr (NBAT == 1) {
+                for (int row = tid; row < nv; row += nthr) {
+                    const T *s = src + (size_t)row * G.nu;
+                    T *d = dst + row;
+                    for (int col = 0; col < pc; ++col) d[col * rowstride] = s[col];
+                }
+            } else {
+                const float inv_pc = 1.0f / (float)pc;
+                for (int q = tid; q < pc * nv; q += nthr) {
+                    const int row = (int)(((float)q + 0.5f) * inv_pc);
+                    const int col = q - row * pc;
+                    dst[col * rowstride + row] = src[(size_t)row * G.nu + col];
+                }
             }
             for (int col = tid; col < pc; col += nthr) {
                 dst[col * rowstride - 1] = T(0);
@@ -116,10 +126,14 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
             }
         }
         // --- stage the strip records of the tile's pixels in slot (p, k - k0(p));
-        // a slot without a record gets n = 0
+        // a slot without a record gets n = 0.  A single volume copies a whole
+        // record per thread (one slot lookup, its registers are free); batches,
+        // which hold more sums, copy one 16-byte chunk per thread.
+        constexpr int CPT = NBAT == 1 ? RCH : 1;  // chunks per thread
+        constexpr int TPS = RCH / CPT;            // threads per slot
         const float inv_rspan = 1.0f / (float)rspan;
-        for (int q = tid; q < TP * rspan * RCH; q += nthr) {
-            const int pk = q / RCH, ch = q - pk * RCH;            // RCH is a constant
+        for (int q = tid; q < TP * rspan * TPS; q += nthr) {
+            const int pk = q / TPS, ch0 = (q - pk * TPS) * CPT;   // TPS is a constant
             const int p = (int)(((float)pk + 0.5f) * inv_rspan);  // exact for pk < 16 rspan, rspan <= 2048
             const int kk = pk - p * rspan;
             const int ix = ix0 + p % TX, iy = iy0 + p / TX;
@@ -135,10 +149,13 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
                                          soff + strip * (RL.n_major_max + 1));
                 }
             }
-            if (pos >= 0)
-                dst[ch] = reinterpret_cast<const uint4 *>(recs + strip * RL.cap + pos)[ch];
-            else if (ch == 0)
+            if (pos >= 0) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(recs + strip * RL.cap + pos);
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) dst[ch0 + c] = src[ch0 + c];
+            } else if (ch0 == 0) {
                 dst[0] = make_uint4(0u, 0u, 0u, 0u);  // lc = 0, n = 0
+            }
         }
         __syncthreads();
         if (!active) continue;
