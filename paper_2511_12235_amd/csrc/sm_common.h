@@ -276,7 +276,18 @@ __host__ __device__ inline float rcp_(float x)
     return 1.0f / x;
 #endif
 }
-__host__ __device__ inline double rcp_(double x) { return 1.0 / x; }
+// FP64: the hardware estimate refined by two Newton steps (each squares the
+// relative error), instead of a correctly rounded division
+__host__ __device__ inline double rcp_(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+#else
+    return 1.0 / x;
+#endif
+}
 
 // Psi(lam) = integral over P of (l' - lam)_+ dA for lam inside [d_0, d_n-1].
 template <typename T>
