@@ -5,4 +5,4 @@
 seeded synthetic inputs.  Submodules are imported on demand so that the
 input generators stay usable without a GPU.
 """
-__all__ = ["projector", "workloads", "solvers", "serve"]
+__all__ = ["projector", "workloads", "serve", "experiments"]

@@ -20,7 +20,7 @@ SOURCES = ["sm_api.hip", "sm_rec.hip", "sm_fwd3d.hip", "sm_back3d.hip", "sm_2d.h
 ARCH = os.environ.get("SM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+         "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I" + os.path.join(HERE, "..", "include")]
 
 
