@@ -116,6 +116,16 @@ sm_status sm_plan_record_bytes(const sm_plan *plan, int64_t *bytes);
  * with any other call on the plan.  No-op in 2D. */
 sm_status sm_plan_keep_records(sm_plan *plan, int64_t max_bytes, void *hip_stream);
 
+/* Launch shape of the 3D operators, fixed at plan creation from the geometry
+ * alone: sm_forward and sm_back process the views in chunks of
+ * *views_per_chunk consecutive views (the last chunk may be shorter; the
+ * strip records of one chunk share the workspace), and the adjoint splits
+ * every chunk of n views into *adjoint_runs runs, run g holding views
+ * [n g / runs, n (g + 1) / runs) of the chunk, each summed into its own
+ * partial volume before the partials are added in order.  In 2D both are
+ * reported as (n_p, 1).  Either output pointer may be NULL. */
+sm_status sm_plan_launch_shape(const sm_plan *plan, int32_t *views_per_chunk, int32_t *adjoint_runs);
+
 /* Device workspace bytes that sm_forward / sm_back need for `batch` volumes
  * (0 in 2D).  In 3D it holds the strip records of one chunk of views (the
  * top-view polygons of Sec. III-B with their chord tables, at most 4 GiB)

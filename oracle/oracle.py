@@ -59,6 +59,8 @@ def lib():
         L.orc_cell_measure.argtypes = [G] + [C.c_int] * 6
         L.orc_ray_gridbox.restype = C.c_double
         L.orc_ray_gridbox.argtypes = [G, C.c_int, C.c_int, C.c_int]
+        L.orc_ray_gridbox_view.restype = None
+        L.orc_ray_gridbox_view.argtypes = [G, C.c_int, dp]
         L.orc_count.restype = C.c_int64
         L.orc_count.argtypes = [G, C.c_int, C.c_int, C.c_double, ip64]
         L.orc_fill.restype = C.c_int
@@ -146,6 +148,13 @@ def cell_measure(g, view, ix, iy, iz, k, r) -> float:
 def ray_gridbox(g, view, k, r) -> float:
     """Exact measure of the whole grid box inside element (k, r)."""
     return float(lib().orc_ray_gridbox(_Bound(g).ref, int(view), int(k), int(r)))
+
+
+def ray_gridbox_view(g, view) -> np.ndarray:
+    """ray_gridbox of every element of one view -> array [det_nz, det_ny]."""
+    out = np.empty((g.det_nz, g.det_ny), dtype=np.float64)
+    lib().orc_ray_gridbox_view(_Bound(g).ref, int(view), _ptr(out))
+    return out
 
 
 def triplets(g, views=None, tau=None):

@@ -486,6 +486,16 @@ double orc_ray_gridbox(const orc_geom *g, int view, int k, int r)
     return orc_clip_box(hx, hy, hz, pl, 4);
 }
 
+/* orc_ray_gridbox for every element of one view, out[r * det_ny + k]
+ * (parallel over rows; each element is the same single clip).            */
+void orc_ray_gridbox_view(const orc_geom *g, int view, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < g->det_nz; ++r)
+        for (int k = 0; k < g->det_ny; ++k)
+            out[(int64_t)r * g->det_ny + k] = orc_ray_gridbox(g, view, k, r);
+}
+
 /* Visit every kept entry (W > tau) of one view, voxels in ascending j, cells
  * of a voxel in ascending (r, k).  Returns the number of entries or -1.    */
 typedef void (*entry_fn)(void *ctx, int64_t i, int64_t j, double w);

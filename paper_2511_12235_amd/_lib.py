@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libsm.so")
 SM_OK, SM_EINVAL, SM_ENOMEM, SM_EDEVICE, SM_EUNSUPPORTED, SM_ERANGE = range(6)
 SM_FP32, SM_FP64 = 0, 1
 
-EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_workspace_size",
+EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_plan_launch_shape",
+            "sm_workspace_size",
             "sm_plan_record_bytes", "sm_plan_keep_records",
             "sm_forward", "sm_back", "sm_line_forward", "sm_line_back",
             "sm_weights_csr", "sm_stored_count", "sm_stored_fill", "sm_stored_apply",
@@ -79,6 +80,8 @@ def lib():
         L.sm_plan_destroy.argtypes = [vp]
         L.sm_plan_sizes.restype = C.c_int
         L.sm_plan_sizes.argtypes = [vp, i64p, i64p]
+        L.sm_plan_launch_shape.restype = C.c_int
+        L.sm_plan_launch_shape.argtypes = [vp, i32p, i32p]
         L.sm_workspace_size.restype = C.c_int
         L.sm_plan_record_bytes.restype = C.c_int
         L.sm_plan_record_bytes.argtypes = [vp, i64p]

@@ -411,6 +411,15 @@ sm_status sm_plan_sizes(const sm_plan *p, int64_t *n_vox, int64_t *n_rays)
     return SM_OK;
 }
 
+sm_status sm_plan_launch_shape(const sm_plan *p, int32_t *views_per_chunk, int32_t *adjoint_runs)
+{
+    if (!p) return fail(SM_EINVAL, "plan is NULL");
+    const bool d3 = p->G.dim == 3;
+    if (views_per_chunk) *views_per_chunk = d3 ? p->RL.views : p->G.n_p;
+    if (adjoint_runs) *adjoint_runs = d3 ? p->L.back_groups : 1;
+    return SM_OK;
+}
+
 static int64_t workspace_bytes(const sm_plan *p, int64_t batch)
 {
     if (p->G.dim != 3) return 0;

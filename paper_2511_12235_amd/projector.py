@@ -96,6 +96,14 @@ class SystemMatrix:
         with torch.cuda.device(self.device):
             _lib.check(_lib.lib().sm_plan_keep_records(self._plan, n, st), "sm_plan_keep_records")
 
+    def launch_shape(self) -> tuple[int, int]:
+        """(views per record chunk, adjoint view runs per chunk) of the 3D
+        operators (sm_plan_launch_shape); (n_p, 1) in 2D."""
+        v, r = C.c_int32(), C.c_int32()
+        _lib.check(_lib.lib().sm_plan_launch_shape(self._plan, C.byref(v), C.byref(r)),
+                   "sm_plan_launch_shape")
+        return v.value, r.value
+
     def workspace_bytes(self, batch: int = 1) -> int:
         n = C.c_int64()
         _lib.check(_lib.lib().sm_workspace_size(self._plan, int(batch), C.byref(n)), "sm_workspace_size")

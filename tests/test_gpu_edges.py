@@ -16,6 +16,8 @@ from paper_2511_12235_amd import _lib
 from paper_2511_12235_amd import workloads as wl
 from paper_2511_12235_amd.projector import SystemMatrix
 
+from _errlog import record
+
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
@@ -107,9 +109,9 @@ def test_one_voxel_one_element(prec):
     A = SystemMatrix(g, prec, device=DEV)
     yg = A.forward(_t(np.full(g.vol_shape, 2.0), prec)).double().cpu().numpy()
     assert W.nnz == 1
-    assert _rel(yg, W @ np.full(g.n_vox, 2.0)) <= TOL[prec]
+    assert record("forward, one voxel one element, %s" % prec, yg, W @ np.full(g.n_vox, 2.0), TOL[prec])[0] <= TOL[prec]
     xg = A.back(_t(np.full(g.sino_shape, 3.0), prec)).double().cpu().numpy()
-    assert _rel(xg, W.T @ np.full(g.n_rays, 3.0)) <= TOL[prec]
+    assert record("adjoint, one voxel one element, %s" % prec, xg, W.T @ np.full(g.n_rays, 3.0), TOL[prec])[0] <= TOL[prec]
 
 
 CASES = {
@@ -143,8 +145,10 @@ def test_extreme_shapes_match_oracle(name, prec):
     A = SystemMatrix(g, prec, device=DEV)
     x = wl.uniform(g.vol_shape, 3) + 0.5
     y = wl.uniform(g.sino_shape, 4)
-    assert _rel(A.forward(_t(x, prec)).cpu().numpy(), W @ x.ravel()) <= TOL[prec]
-    assert _rel(A.back(_t(y, prec)).cpu().numpy(), W.T @ y.ravel()) <= TOL[prec]
+    assert record("forward, edge shape %s, %s" % (name, prec), A.forward(_t(x, prec)).cpu().numpy(), W @ x.ravel(),
+                  TOL[prec])[0] <= TOL[prec]
+    assert record("adjoint, edge shape %s, %s" % (name, prec), A.back(_t(y, prec)).cpu().numpy(), W.T @ y.ravel(),
+                  TOL[prec])[0] <= TOL[prec]
 
 
 def test_batch_limit():

@@ -16,6 +16,8 @@ from oracle import solvers as SV
 from paper_2511_12235_amd import workloads as wl
 from paper_2511_12235_amd.projector import SystemMatrix
 
+from _errlog import record
+
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
@@ -77,8 +79,9 @@ def test_line_matches_oracle(name, k, weight, prec):
     y = wl.uniform(g.sino_shape, 5)
     yg = A.line_forward(_t(x, prec), k, weight).cpu().numpy()
     xg = A.line_back(_t(y, prec), k, weight).cpu().numpy()
-    assert _rel(yg, W @ x.ravel()) <= TOL[prec]
-    assert _rel(xg, W.T @ y.ravel()) <= TOL[prec]
+    assert record("line forward k=%d %s, %s %s" % (k, weight, name, prec), yg, W @ x.ravel(), TOL[prec])[0] <= TOL[prec]
+    assert record("line adjoint k=%d %s, %s %s" % (k, weight, name, prec), xg, W.T @ y.ravel(),
+                  TOL[prec])[0] <= TOL[prec]
 
 
 @pytest.mark.parametrize("name", ["fan", "cone", "cone_axis"])
@@ -148,14 +151,14 @@ def test_line_full_size_sampled():
            for _ in range(5)]
     els.append((0, g.det_nz // 2, g.det_ny // 2))
     yo = LN.forward_rows(g, 1, "length", x, els)
-    assert _rel([y[v, r, m] for v, r, m in els], yo) <= 1e-5
+    assert record("line forward rays, c3 fp32", [y[v, r, m] for v, r, m in els], yo, 1e-5)[0] <= 1e-5
     ys = wl.uniform(g.sino_shape, 14)
     xb = A.line_back(_t(ys, "fp32"), 1, "measure").cpu().numpy().ravel()
     # voxels of the central half of the grid (the corners lie outside the cone)
     q = rng.integers(g.nx // 4, 3 * g.nx // 4, size=(4, 3))
     vox = (q[:, 0] * g.ny + q[:, 1]) * g.nx + q[:, 2]
     xo = LN.back_voxels(g, 1, "measure", ys, vox)
-    assert _rel(xb[vox], xo) <= 1e-5
+    assert record("line adjoint voxels, c3 fp32", xb[vox], xo, 1e-5)[0] <= 1e-5
     yw = A.line_forward(_t(x, "fp32"), 1, "measure").double().cpu().numpy()
     lhs, rhs = float(np.vdot(yw, ys)), float(np.vdot(x, xb))
     assert abs(lhs - rhs) <= 1e-6 * abs(lhs)

@@ -14,15 +14,11 @@ from oracle import oracle as O
 from paper_2511_12235_amd import workloads as wl
 from paper_2511_12235_amd.projector import SystemMatrix
 
+from _errlog import note, record
+
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
-
-
-def _rel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def _t(a, prec):
@@ -88,8 +84,8 @@ def test_forward_adjoint_match_oracle(name, prec, oracle_mats):
     yg = A.forward(_t(x, prec)).cpu().numpy()
     xg = A.back(_t(y, prec)).cpu().numpy()
     torch.cuda.synchronize()
-    assert _rel(yg.ravel(), W @ x.ravel()) <= TOL[prec]
-    assert _rel(xg.ravel(), W.T @ y.ravel()) <= TOL[prec]
+    assert record("forward W x, %s %s" % (name, prec), yg, W @ x.ravel(), TOL[prec])[0] <= TOL[prec]
+    assert record("adjoint W^T y, %s %s" % (name, prec), xg, W.T @ y.ravel(), TOL[prec])[0] <= TOL[prec]
 
 
 @pytest.mark.parametrize("name", SMALL)
@@ -101,10 +97,10 @@ def test_csr_pattern_and_values(name, oracle_mats):
     rp, ci, va = A.weights_csr("fp64")
     assert np.array_equal(rp, W.indptr.astype(np.int64))
     assert np.array_equal(ci, W.indices.astype(np.int32))
-    assert _rel(va, W.data) <= 1e-12
+    assert record("CSR values, %s fp64" % name, va, W.data, 1e-12)[0] <= 1e-12
     rp32, ci32, va32 = A.weights_csr("fp32")
     assert np.array_equal(rp32, rp) and np.array_equal(ci32, ci)
-    assert _rel(va32, W.data) <= 1e-5
+    assert record("CSR values, %s fp32" % name, va32, W.data, 1e-5)[0] <= 1e-5
 
 
 @pytest.mark.parametrize("name", ["c1_fan64", "cone_small", "cone_degenerate", "cone_aniso_offset",
@@ -129,7 +125,9 @@ def test_dot_product(name, prec):
     Wty = A.back(_t(y, prec)).double().cpu().numpy()
     lhs, rhs = float(np.vdot(Wx, y)), float(np.vdot(x, Wty))
     bound = 1e-12 if prec == "fp64" else 1e-6
-    assert abs(lhs - rhs) <= bound * np.linalg.norm(Wx) * np.linalg.norm(y)
+    mis = abs(lhs - rhs) / (np.linalg.norm(Wx) * np.linalg.norm(y))
+    note("dot test, %s %s" % (name, prec), mis, mis, 1, bound, kind="dot")
+    assert mis <= bound
 
 
 @pytest.mark.parametrize("name", ["fan_odd", "cone_small"])
@@ -160,7 +158,8 @@ def test_fp32_forward_magnitudes(name, oracle_mats):
     x = wl.ellipse_phantom(g, 5, seed=7) + 0.1 * wl.uniform(g.vol_shape, 8)
     for s in (1e-30, 1e-8, 1e8, 1e30):
         yg = A.forward(_t(x * s, "fp32")).double().cpu().numpy()
-        assert _rel(yg.ravel(), W @ (x * s).ravel()) <= TOL["fp32"], s
+        assert record("forward, x scaled by %.0e, %s fp32" % (s, name), yg, W @ (x * s).ravel(),
+                      TOL["fp32"])[0] <= TOL["fp32"], s
     X = np.stack([x * 1e-20, x, x * 1e20, np.zeros_like(x)])
     yb = A.forward(_t(X, "fp32")).cpu().numpy()
     for i in range(len(X)):
@@ -231,7 +230,7 @@ def test_full_size_sampled(which):
     extra = (views * g.det_nz + g.det_nz // 2) * g.det_ny + g.det_ny // 2
     rays = np.concatenate([rays, extra])
     yo = O.forward_rays(g, x, rays)
-    assert _rel(y[rays], yo) <= 1e-5
+    assert record("forward rays, random, %s fp32" % which, y[rays], yo, 1e-5)[0] <= 1e-5
     # row sums of W against the grid-box clip
     ones = A.forward(torch.ones(g.vol_shape, device=DEV)).cpu().numpy().ravel()
     gb = []
@@ -239,13 +238,13 @@ def test_full_size_sampled(which):
         v, rem = divmod(int(i), g.det_nz * g.det_ny)
         r, k = divmod(rem, g.det_ny)
         gb.append(O.ray_gridbox(g, v, k, r))
-    assert _rel(ones[rays[:16]], gb) <= 1e-5
+    assert record("W 1 = grid-box clip, 16 rays, %s fp32" % which, ones[rays[:16]], gb, 1e-5)[0] <= 1e-5
     # adjoint on sampled voxels
     ys = wl.uniform(g.sino_shape, 9)
     xb = A.back(_t(ys, "fp32")).cpu().numpy().ravel()
     vox = rng.choice(g.n_vox, size=48, replace=False)
     xo = O.back(g, ys, vox)
-    assert _rel(xb[vox], xo) <= 1e-5
+    assert record("adjoint voxels, random, %s fp32" % which, xb[vox], xo, 1e-5)[0] <= 1e-5
 
 
 def test_nnz_count_beyond_2pow32_work_items():

@@ -20,6 +20,8 @@ from paper_2511_12235_amd import _lib
 from paper_2511_12235_amd import workloads as wl
 from paper_2511_12235_amd.projector import SystemMatrix
 
+from _errlog import note, record
+
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 TOL = {"fp64": 1e-9, "fp32": 1e-4}
@@ -79,7 +81,7 @@ def test_cgls(name, prec):
     x_ref, h_ref = S.cgls(W, y, np.zeros(g.n_vox), iters, lam=lam, s=s)
     A = SystemMatrix(g, prec, device=DEV)
     x, h = A.cgls(_t(y, prec), iters, lam=lam, wscale=s)
-    assert _rel(x.cpu().numpy(), x_ref) <= TOL[prec]
+    assert record("CGLS %d steps, %s %s" % (iters, name, prec), x.cpu().numpy(), x_ref, TOL[prec])[0] <= TOL[prec]
     assert _rel(h.cpu().numpy()[:, 0], h_ref) <= (1e-9 if prec == "fp64" else 1e-3)
 
 
@@ -95,7 +97,7 @@ def test_nag(name, prec):
     A = SystemMatrix(g, prec, device=DEV)
     nd = torch.tensor([norm], dtype=torch.float64, device=DEV)
     x, h = A.nag(_t(y, prec), 10, nd, lam=lam, wscale=s)
-    assert _rel(x.cpu().numpy(), x_ref) <= TOL[prec]
+    assert record("NAG 10 steps, %s %s" % (name, prec), x.cpu().numpy(), x_ref, TOL[prec])[0] <= TOL[prec]
     assert _rel(h.cpu().numpy()[:, 0], h_ref) <= (1e-9 if prec == "fp64" else 1e-3)
 
 
@@ -133,9 +135,10 @@ def test_full_size_reconstruction_precision():
     """The 256^3 reconstruction workload: y = W x_true with Poisson noise at
     1e5 photons per ray, 30 CGLS steps and 30 NAG steps on the normalised
     operator (lambda = 1e-3), FP32 plan against FP64 plan (the FP64 path is
-    the one pinned to the oracle above).  Prints the relative differences and
-    the relative errors to x_true; bounds them loosely (the FP32 floor of the
-    Krylov recurrence, see the module docstring)."""
+    the one pinned to the oracle above and, at this size, in
+    test_gpu_fullsize.py).  Prints the relative differences and the relative
+    errors to x_true; bounds them at 1e-4 (the FP32 floor of the Krylov
+    recurrence, see the module docstring)."""
     g = wl.c3_cone256()
     print("[case] 256^3 reconstruction", flush=True)
     x_true = wl.ellipse_phantom(g, 10, seed=2)
@@ -164,5 +167,8 @@ def test_full_size_reconstruction_precision():
         g0, g1 = out["fp64"][i + 2][0], out["fp64"][i + 2][-1]
         print("[recon] %s: fp32 vs fp64 %.3e; error to x_true fp64 %.4f fp32 %.4f; |grad|^2 %.3e -> %.3e"
               % (name, d, e64, e32, g0, g1), flush=True)
-        assert d <= 5e-2
-        assert abs(e32 - e64) <= 5e-2
+        note("256^3 %s, 30 steps: FP32 plan vs FP64 plan" % name, d, d, int(xt.size), 1e-4)
+        # measured 6.5e-6 (CGLS) and 1.4e-6 (NAG): the bound leaves a factor
+        # of about 15 for the FP32 floor of the recurrences
+        assert d <= 1e-4
+        assert abs(e32 - e64) <= 1e-4

@@ -10,7 +10,9 @@ from oracle import oracle as O
 from paper_2511_12235_amd import workloads as wl
 from paper_2511_12235_amd.projector import StoredMatrix, SystemMatrix
 
-from test_gpu_parity import GEOMS, TOL, _rel, _t
+from _errlog import errors, record
+
+from test_gpu_parity import GEOMS, TOL, _t
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -46,10 +48,10 @@ def test_stored_products_match_oracle_and_matrix_free(name, prec):
     y = wl.uniform(g.sino_shape, 4)
     ys = S.forward(_t(x, prec)).cpu().numpy()
     xs = S.back(_t(y, prec)).cpu().numpy()
-    assert _rel(ys.ravel(), W @ x.ravel()) <= TOL[prec]
-    assert _rel(xs.ravel(), W.T @ y.ravel()) <= TOL[prec]
-    assert _rel(ys, A.forward(_t(x, prec)).cpu().numpy()) <= 2 * TOL[prec]
-    assert _rel(xs, A.back(_t(y, prec)).cpu().numpy()) <= 2 * TOL[prec]
+    assert record("stored W x, %s %s" % (name, prec), ys, W @ x.ravel(), TOL[prec])[0] <= TOL[prec]
+    assert record("stored W^T y, %s %s" % (name, prec), xs, W.T @ y.ravel(), TOL[prec])[0] <= TOL[prec]
+    assert errors(ys, A.forward(_t(x, prec)).cpu().numpy())[0] <= 2 * TOL[prec]
+    assert errors(xs, A.back(_t(y, prec)).cpu().numpy())[0] <= 2 * TOL[prec]
     # deterministic, and batches are independent products
     assert np.array_equal(ys, S.forward(_t(x, prec)).cpu().numpy())
     xb = np.stack([x, 2.0 * x])
@@ -64,5 +66,5 @@ def test_stored_medium_size_matches_matrix_free():
     S = StoredMatrix(A)
     x = torch.from_numpy(wl.ellipse_phantom(g, 10, seed=1)).to(DEV, torch.float32)
     y = torch.from_numpy(wl.uniform(g.sino_shape, 2)).to(DEV, torch.float32)
-    assert _rel(S.forward(x).cpu().numpy(), A.forward(x).cpu().numpy()) <= 2e-5
-    assert _rel(S.back(y).cpu().numpy(), A.back(y).cpu().numpy()) <= 2e-5
+    assert errors(S.forward(x).cpu().numpy(), A.forward(x).cpu().numpy())[0] <= 2e-5
+    assert errors(S.back(y).cpu().numpy(), A.back(y).cpu().numpy())[0] <= 2e-5

@@ -197,6 +197,16 @@ def test_row_sums_equal_gridbox_clip():
 # P5: a single tall detector row turns the 3D measure into c times the 2D area
 # ----------------------------------------------------------------------------
 
+def test_gridbox_view_equals_single_clips():
+    """The per-view batch of grid-box clips is the single clip per element."""
+    for g in (_tiny3d(trig=DEGENERATE_TRIG), _tiny2d(trig=DEGENERATE_TRIG)):
+        for view in (0, 3):
+            got = O.ray_gridbox_view(g, view)
+            exp = np.array([[O.ray_gridbox(g, view, k, r) for k in range(g.det_ny)]
+                            for r in range(g.det_nz)])
+            assert np.array_equal(got, exp)
+
+
 def test_3d_reduces_to_2d():
     phi = np.array([0.0, 0.5, 2.2, np.pi / 2 + 1e-7])
     g2 = wl.make_geometry(2, (5, 4), (1.0, 1.2), 4, 20.0, 10.0, (12,), (0.9,), phi=phi)
