@@ -154,6 +154,28 @@ sm_status sm_forward(const sm_plan *plan, const void *x, void *y, int32_t batch,
 sm_status sm_back(const sm_plan *plan, const void *y, void *x, int32_t batch, void *ws,
                   int64_t ws_bytes, void *hip_stream);
 
+/* sm_forward (adjoint == 0) or sm_back (adjoint == 1) without a workspace,
+ * for callers that cannot allocate device memory: code under HIP stream
+ * capture, serving loops and hosts that forbid hipMalloc.  Same plan, layouts,
+ * stream, overwrite and precision rules as those entry points; calls no
+ * allocator.  The workspace lives in a static device array of
+ * SM_NOALLOC_SCRATCH_BYTES per device, which the library holds from the
+ * first call on a device until the process ends.  It must hold the volume
+ * buffers of the call (3D forward: FP64 prefix sums, (nz + 1) nx ny batch
+ * doubles; 3D adjoint: nz nx ny batch elements per view run) plus, unless the
+ * plan keeps its records (sm_plan_keep_records), the strip records of at
+ * least one view; otherwise SM_ERANGE, with the sizes in sm_last_error().
+ * Records are rebuilt in chunks of as many views as fit (the adjoint may also
+ * sum fewer view runs), so adjoint results can differ from sm_back's in the
+ * rounding order of their sums only; forward results are bitwise sm_forward's.
+ * 2D plans need no scratch.  Calls on one device share the array: calls that
+ * overlap in time on one device (several streams or host threads) race and
+ * must be serialised by the caller.  SM_EINVAL for adjoint not in {0, 1} and
+ * the argument errors of sm_forward. */
+#define SM_NOALLOC_SCRATCH_BYTES ((int64_t)128 << 20)
+sm_status sm_apply_noalloc(const sm_plan *plan, int32_t adjoint, const void *in, void *out,
+                           int32_t batch, void *hip_stream);
+
 /* The explicit matrix W in CSR form (Sec. I: W in R^{M x N}) for small
  * problems, written to host arrays.  Entries with W_ij <= tau_keep =
  * 1e-12 * (voxel measure) are treated as exact zeros; the pattern is decided

@@ -19,7 +19,7 @@ SM_FP32, SM_FP64 = 0, 1
 EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_plan_launch_shape",
             "sm_workspace_size",
             "sm_plan_record_bytes", "sm_plan_keep_records",
-            "sm_forward", "sm_back", "sm_line_forward", "sm_line_back",
+            "sm_forward", "sm_back", "sm_apply_noalloc", "sm_line_forward", "sm_line_back",
             "sm_weights_csr", "sm_stored_count", "sm_stored_fill", "sm_stored_apply",
             "sm_footprints", "sm_solver_workspace_size", "sm_power_norm",
             "sm_cgls", "sm_nag", "sm_line_power_norm", "sm_line_nag", "sm_timing_enable", "sm_timing_read",
@@ -28,6 +28,7 @@ EXPORTED = ("sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_plan_launc
 SM_SOLVER_CGLS, SM_SOLVER_NAG, SM_SOLVER_POWER = range(3)
 SM_LINE_LENGTH, SM_LINE_MEASURE = range(2)
 SM_LINE_MAX_K = 64
+SM_NOALLOC_SCRATCH_BYTES = 128 << 20  # include/sm.h
 
 # sm_kernel ids (timing)
 KERNELS = ("records", "forward", "adjoint", "prefix", "transpose")
@@ -92,6 +93,8 @@ def lib():
         L.sm_forward.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_int64, vp]
         L.sm_back.restype = C.c_int
         L.sm_back.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_int64, vp]
+        L.sm_apply_noalloc.restype = C.c_int
+        L.sm_apply_noalloc.argtypes = [vp, C.c_int32, vp, vp, C.c_int32, vp]
         L.sm_line_forward.restype = C.c_int
         L.sm_line_forward.argtypes = [vp, C.c_int32, C.c_int, vp, vp, C.c_int32, vp]
         L.sm_line_back.restype = C.c_int

@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsm.so")
 SOURCES = ["sm_api.hip", "sm_rec.hip", "sm_fwd3d.hip", "sm_back3d.hip", "sm_2d.hip",
            "sm_transpose.hip", "sm_csr.hip", "sm_solve.hip", "sm_stored.hip",
-           "sm_line.hip"]
+           "sm_line.hip", "sm_noalloc.hip"]
 ARCH = os.environ.get("SM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

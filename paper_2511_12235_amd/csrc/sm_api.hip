@@ -123,6 +123,148 @@ sm_status set_error(sm_status s, const char *fmt, ...)
 sm_status check_plan_device(const sm_plan *p) { return check_device(p); }
 }  // namespace smk
 
+namespace smk {
+
+// Volume buffers of one call, behind the records of a chunk: the forward's
+// FP64 prefix sums and max |x| per batch element, the adjoint's `groups`
+// partial volumes.
+int64_t fwd_volume_bytes(const sm_plan *p, int64_t batch)
+{
+    const int64_t npix = (int64_t)p->G.nx * p->G.ny;
+    return smk::align256(npix * batch * (int64_t)(p->G.nz + 1) * (int64_t)sizeof(double)) +
+           smk::align256(batch * (int64_t)sizeof(unsigned));
+}
+
+int64_t back_volume_bytes(const sm_plan *p, int64_t batch, int groups)
+{
+    const int64_t npix = (int64_t)p->G.nx * p->G.ny;
+    const int64_t es = p->prec == SM_FP64 ? 8 : 4;
+    return (int64_t)groups * npix * batch * p->G.nz * es;
+}
+
+int64_t workspace_bytes(const sm_plan *p, int64_t batch)
+{
+    if (p->G.dim != 3) return 0;
+    const int64_t fwd = fwd_volume_bytes(p, batch);
+    const int64_t adj = back_volume_bytes(p, batch, p->L.back_groups);
+    // the records of one chunk precede the volume buffer unless the plan keeps them
+    return (p->rec_cache ? 0 : p->RL.data_off) + (fwd > adj ? fwd : adj);
+}
+
+int64_t record_bytes(const sm_plan *p)
+{
+    if (p->G.dim != 3) return 0;
+    const int64_t chunks = (p->G.n_p + p->RL.views - 1) / p->RL.views;
+    return chunks * p->RL.data_off;
+}
+
+// y = W x for a 3D plan: records of each chunk of RL.views views (from the
+// plan's copy when it keeps them, else built into `recws`), the volume
+// buffer at `vol`.
+hipError_t run_forward3d(const sm_plan *p, const smk::RecLayout &RL, const void *x, void *y,
+                         int batch, void *recws, void *vol, hipStream_t st)
+{
+    const bool f64 = p->prec == SM_FP64;
+    double *P = (double *)vol;
+    const int64_t npix = (int64_t)p->G.nx * p->G.ny;
+    unsigned *xmax = (unsigned *)((char *)P + smk::align256(npix * batch * (int64_t)(p->G.nz + 1) *
+                                                            (int64_t)sizeof(double)));
+    int q = tm_begin(p, SM_KERNEL_PREFIX, st);
+    hipError_t e = smk::launch_prefix_columns(x, P, xmax, f64, batch, p->G.nz, p->G.ny, p->G.nx, st);
+    tm_end(p, q, st);
+    for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
+        const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
+        void *rws = recws;
+        if (p->rec_cache) {
+            rws = (char *)p->rec_cache + (int64_t)(v0 / RL.views) * RL.data_off;
+        } else {
+            q = tm_begin(p, SM_KERNEL_RECORDS, st);
+            e = smk::launch_records(p->G, RL, f64, v0, nvc, rws, st);
+            tm_end(p, q, st);
+            if (e != hipSuccess) break;
+        }
+        q = tm_begin(p, SM_KERNEL_FORWARD, st);
+        e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, rws, P, xmax, y, batch, st);
+        tm_end(p, q, st);
+    }
+    return e;
+}
+
+// x = W^T y for a 3D plan, records as run_forward3d; L.back_groups partial
+// volumes at `vol`.
+hipError_t run_back3d(const sm_plan *p, const smk::RecLayout &RL, const LaunchCfg &L, const void *y,
+                      void *x, int batch, void *recws, void *vol, hipStream_t st)
+{
+    const bool f64 = p->prec == SM_FP64;
+    hipError_t e = hipSuccess;
+    int q;
+    for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
+        const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
+        void *rws = recws;
+        if (p->rec_cache) {
+            rws = (char *)p->rec_cache + (int64_t)(v0 / RL.views) * RL.data_off;
+        } else {
+            q = tm_begin(p, SM_KERNEL_RECORDS, st);
+            e = smk::launch_records(p->G, RL, f64, v0, nvc, rws, st);
+            tm_end(p, q, st);
+            if (e != hipSuccess) break;
+        }
+        q = tm_begin(p, SM_KERNEL_ADJOINT, st);
+        e = smk::launch_back3d(p->G, L, RL, f64, v0, nvc, rws, y, vol, batch, v0 == 0, st);
+        tm_end(p, q, st);
+    }
+    if (e == hipSuccess) {
+        q = tm_begin(p, SM_KERNEL_TRANSPOSE, st);
+        e = smk::launch_from_columns(vol, x, f64 ? 8 : 4, batch, p->G.nz, p->G.ny, p->G.nx,
+                                     L.back_groups, st);
+        tm_end(p, q, st);
+    }
+    return e;
+}
+
+hipError_t run_apply2d(const sm_plan *p, bool adjoint, const void *in, void *out, int batch,
+                       hipStream_t st)
+{
+    const bool f64 = p->prec == SM_FP64;
+    const int q = tm_begin(p, adjoint ? SM_KERNEL_ADJOINT : SM_KERNEL_FORWARD, st);
+    const hipError_t e = adjoint ? smk::launch_back2d(p->G, f64, in, out, batch, st)
+                                 : smk::launch_fwd2d(p->G, f64, in, out, batch, st);
+    tm_end(p, q, st);
+    return e;
+}
+
+// Arguments of an operator call other than the workspace.
+sm_status check_operands(const sm_plan *p, const void *in, void *out, int32_t batch)
+{
+    if (!p) return fail(SM_EINVAL, "plan is NULL");
+    if (!in || !out) return fail(SM_EINVAL, "input or output pointer is NULL");
+    if (batch < 1) return fail(SM_EINVAL, "batch must be >= 1");
+    if (p->G.dim == 3 && p->G.ny * (int64_t)batch > 65535) return fail(SM_EUNSUPPORTED, "ny * batch > 65535");
+    return check_device(p);
+}
+
+sm_status check_apply(const sm_plan *p, const void *in, void *out, int32_t batch, void *ws,
+                      int64_t ws_bytes)
+{
+    sm_status s = check_operands(p, in, out, batch);
+    if (s != SM_OK) return s;
+    if (p->G.dim == 3) {
+        const int64_t need = workspace_bytes(p, batch);
+        if (!ws || ws_bytes < need)
+            return fail(SM_EINVAL, "workspace too small: need %lld bytes", (long long)need);
+    }
+    return SM_OK;
+}
+
+}  // namespace smk
+
+using smk::check_apply;
+using smk::record_bytes;
+using smk::run_apply2d;
+using smk::run_back3d;
+using smk::run_forward3d;
+using smk::workspace_bytes;
+
 extern "C" {
 
 const char *sm_status_str(sm_status s)
@@ -352,8 +494,6 @@ sm_status sm_plan_destroy(sm_plan *p)
     return SM_OK;
 }
 
-static int64_t record_bytes(const sm_plan *p);
-
 sm_status sm_plan_record_bytes(const sm_plan *p, int64_t *bytes)
 {
     if (!p) return fail(SM_EINVAL, "plan is NULL");
@@ -420,34 +560,6 @@ sm_status sm_plan_launch_shape(const sm_plan *p, int32_t *views_per_chunk, int32
     return SM_OK;
 }
 
-static int64_t workspace_bytes(const sm_plan *p, int64_t batch)
-{
-    if (p->G.dim != 3) return 0;
-    const int64_t npix = (int64_t)p->G.nx * p->G.ny;
-    const int64_t es = p->prec == SM_FP64 ? 8 : 4;
-    // prefix sums, then max |x| per batch element
-    const int64_t fwd = smk::align256(npix * batch * (int64_t)(p->G.nz + 1) * (int64_t)sizeof(double)) +
-                        smk::align256(batch * (int64_t)sizeof(unsigned));
-    const int64_t adj = (int64_t)p->L.back_groups * npix * batch * p->G.nz * es;
-    // the records of one chunk precede the volume buffer unless the plan keeps them
-    return (p->rec_cache ? 0 : p->RL.data_off) + (fwd > adj ? fwd : adj);
-}
-
-// Records of the chunk starting at view v0: the plan's copy, or the workspace
-// (then rebuilt by the caller before use).
-static void *chunk_records(const sm_plan *p, void *ws, int v0)
-{
-    if (!p->rec_cache) return ws;
-    return (char *)p->rec_cache + (int64_t)(v0 / p->RL.views) * p->RL.data_off;
-}
-
-static int64_t record_bytes(const sm_plan *p)
-{
-    if (p->G.dim != 3) return 0;
-    const int64_t chunks = (p->G.n_p + p->RL.views - 1) / p->RL.views;
-    return chunks * p->RL.data_off;
-}
-
 sm_status sm_workspace_size(const sm_plan *p, int32_t batch, int64_t *bytes)
 {
     if (!p) return fail(SM_EINVAL, "plan is NULL");
@@ -457,56 +569,18 @@ sm_status sm_workspace_size(const sm_plan *p, int32_t batch, int64_t *bytes)
     return SM_OK;
 }
 
-static sm_status check_apply(const sm_plan *p, const void *in, void *out, int32_t batch, void *ws,
-                             int64_t ws_bytes)
-{
-    if (!p) return fail(SM_EINVAL, "plan is NULL");
-    if (!in || !out) return fail(SM_EINVAL, "input or output pointer is NULL");
-    if (batch < 1) return fail(SM_EINVAL, "batch must be >= 1");
-    if (p->G.dim == 3) {
-        const int64_t need = workspace_bytes(p, batch);
-        if (!ws || ws_bytes < need)
-            return fail(SM_EINVAL, "workspace too small: need %lld bytes", (long long)need);
-        if (p->G.ny * (int64_t)batch > 65535) return fail(SM_EUNSUPPORTED, "ny * batch > 65535");
-    }
-    return check_device(p);
-}
-
 sm_status sm_forward(const sm_plan *p, const void *x, void *y, int32_t batch, void *ws,
                      int64_t ws_bytes, void *stream)
 {
     sm_status s = check_apply(p, x, y, batch, ws, ws_bytes);
     if (s != SM_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    const bool f64 = p->prec == SM_FP64;
     hipError_t e;
-    int q;
     if (p->G.dim == 2) {
-        q = tm_begin(p, SM_KERNEL_FORWARD, st);
-        e = smk::launch_fwd2d(p->G, f64, x, y, batch, st);
-        tm_end(p, q, st);
+        e = run_apply2d(p, false, x, y, batch, st);
     } else {
-        const smk::RecLayout &RL = p->RL;
-        double *P = (double *)((char *)ws + (p->rec_cache ? 0 : RL.data_off));
-        const int64_t npix = (int64_t)p->G.nx * p->G.ny;
-        unsigned *xmax = (unsigned *)((char *)P + smk::align256(npix * batch * (int64_t)(p->G.nz + 1) *
-                                                                (int64_t)sizeof(double)));
-        q = tm_begin(p, SM_KERNEL_PREFIX, st);
-        e = smk::launch_prefix_columns(x, P, xmax, f64, batch, p->G.nz, p->G.ny, p->G.nx, st);
-        tm_end(p, q, st);
-        for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
-            const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
-            void *rws = chunk_records(p, ws, v0);
-            if (!p->rec_cache) {
-                q = tm_begin(p, SM_KERNEL_RECORDS, st);
-                e = smk::launch_records(p->G, RL, f64, v0, nvc, rws, st);
-                tm_end(p, q, st);
-                if (e != hipSuccess) break;
-            }
-            q = tm_begin(p, SM_KERNEL_FORWARD, st);
-            e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, rws, P, xmax, y, batch, st);
-            tm_end(p, q, st);
-        }
+        void *vol = (char *)ws + (p->rec_cache ? 0 : p->RL.data_off);
+        e = run_forward3d(p, p->RL, x, y, batch, ws, vol, st);
     }
     return e == hipSuccess ? SM_OK : hip_fail(e, "sm_forward launch");
 }
@@ -517,36 +591,12 @@ sm_status sm_back(const sm_plan *p, const void *y, void *x, int32_t batch, void 
     sm_status s = check_apply(p, y, x, batch, ws, ws_bytes);
     if (s != SM_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    const bool f64 = p->prec == SM_FP64;
     hipError_t e;
-    int q;
     if (p->G.dim == 2) {
-        q = tm_begin(p, SM_KERNEL_ADJOINT, st);
-        e = smk::launch_back2d(p->G, f64, y, x, batch, st);
-        tm_end(p, q, st);
+        e = run_apply2d(p, true, y, x, batch, st);
     } else {
-        const smk::RecLayout &RL = p->RL;
-        void *xt = (char *)ws + (p->rec_cache ? 0 : RL.data_off);
-        e = hipSuccess;
-        for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
-            const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
-            void *rws = chunk_records(p, ws, v0);
-            if (!p->rec_cache) {
-                q = tm_begin(p, SM_KERNEL_RECORDS, st);
-                e = smk::launch_records(p->G, RL, f64, v0, nvc, rws, st);
-                tm_end(p, q, st);
-                if (e != hipSuccess) break;
-            }
-            q = tm_begin(p, SM_KERNEL_ADJOINT, st);
-            e = smk::launch_back3d(p->G, p->L, RL, f64, v0, nvc, rws, y, xt, batch, v0 == 0, st);
-            tm_end(p, q, st);
-        }
-        if (e == hipSuccess) {
-            q = tm_begin(p, SM_KERNEL_TRANSPOSE, st);
-            e = smk::launch_from_columns(xt, x, f64 ? 8 : 4, batch, p->G.nz, p->G.ny, p->G.nx,
-                                         p->L.back_groups, st);
-            tm_end(p, q, st);
-        }
+        void *vol = (char *)ws + (p->rec_cache ? 0 : p->RL.data_off);
+        e = run_back3d(p, p->RL, p->L, y, x, batch, ws, vol, st);
     }
     return e == hipSuccess ? SM_OK : hip_fail(e, "sm_back launch");
 }

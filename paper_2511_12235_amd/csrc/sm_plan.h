@@ -38,4 +38,23 @@ namespace smk {
 sm_status set_error(sm_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 // SM_OK when the plan's device is current.
 sm_status check_plan_device(const sm_plan *p);
+
+// Operator plumbing of sm_forward / sm_back (sm_api.hip), shared with the
+// entry point that brings its own scratch memory.
+// Bytes of the forward's volume buffer (prefix sums, max |x|) and of the
+// adjoint's `groups` partial volumes, for `batch` volumes.
+int64_t fwd_volume_bytes(const sm_plan *p, int64_t batch);
+int64_t back_volume_bytes(const sm_plan *p, int64_t batch, int groups);
+// Argument checks of an operator call other than its workspace (status and
+// sm_last_error as the entry points).
+sm_status check_operands(const sm_plan *p, const void *in, void *out, int32_t batch);
+// 3D operators with the records of each chunk of RL.views views taken from
+// the plan's kept copy or built into `recws` (RL.data_off bytes), and the
+// volume buffer at `vol`.
+hipError_t run_forward3d(const sm_plan *p, const RecLayout &RL, const void *x, void *y, int batch,
+                         void *recws, void *vol, hipStream_t st);
+hipError_t run_back3d(const sm_plan *p, const RecLayout &RL, const LaunchCfg &L, const void *y,
+                      void *x, int batch, void *recws, void *vol, hipStream_t st);
+hipError_t run_apply2d(const sm_plan *p, bool adjoint, const void *in, void *out, int batch,
+                       hipStream_t st);
 }  // namespace smk

@@ -149,6 +149,19 @@ class SystemMatrix:
 
     __matmul__ = forward
 
+    def apply_noalloc(self, inp: torch.Tensor, adjoint: bool, out: torch.Tensor) -> torch.Tensor:
+        """W inp (adjoint=False) or W^T inp (adjoint=True) into `out` through
+        sm_apply_noalloc: no workspace and no allocation, the library's static
+        scratch array instead (calls on one device must not overlap)."""
+        src, dst = (self.sino_shape, self.vol_shape) if adjoint else (self.vol_shape, self.sino_shape)
+        B = self._check(inp, src, "input")
+        if self._check(out, dst, "out") != B or out.dim() != inp.dim():
+            raise ValueError("out batch does not match the input")
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(_lib.lib().sm_apply_noalloc(self._plan, 1 if adjoint else 0, inp.data_ptr(),
+                                               out.data_ptr(), B, st), "sm_apply_noalloc")
+        return out
+
     # ------------------------------------------------- line-based comparison
     @staticmethod
     def _line_weight(weight: str) -> int:
