@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--digest-valu", metavar="CSV")
     ap.add_argument("--kernel", default="back3d_kernel")
+    ap.add_argument("--nnz", type=int, default=0,
+                    help="nonzero pairs of the profiled operator (--digest-valu: lane instructions per pair)")
     ap.add_argument("--out")
     ap.add_argument("--command", default="")
     return ap.parse_args()
@@ -189,12 +191,18 @@ def digest_counters(args):
 def digest_valu(args):
     """Vector-instruction issue of the 3D kernels from one rocprofv3 --pmc pass
     (SQ_INSTS_VALU, SQ_WAVES): a wave64 VALU instruction occupies its SIMD for
-    4 cycles, so issue-bound time = insts x 4 / (1024 SIMDs x 2.4 GHz)."""
+    4 cycles, so issue-bound time = insts x 4 / (1024 SIMDs x 2.4 GHz).  With
+    --nnz (the operator's nonzero pairs, which one direction's launches cover
+    once) it also reports VALU lane-instructions (64 per wave instruction) per
+    pair."""
     rows = _rows(args.digest_valu)
     lines = ["# VALU issue of the 3D kernels from one rocprofv3 --pmc pass",
              "command: %s" % args.command,
-             "issue_fraction = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x duration)", "",
-             "%-16s %5s %12s %16s %12s %9s" % ("kernel", "calls", "avg_ms", "valu_per_call", "waves", "issue")]
+             "issue_fraction = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x 2.4 GHz x duration)",
+             "lane_insts_per_pair = 64 x SQ_INSTS_VALU summed over the launches / nnz"
+             + (" (nnz = %d)" % args.nnz if args.nnz else " (no --nnz given)"), "",
+             "%-16s %5s %12s %16s %12s %9s %10s" % ("kernel", "calls", "avg_ms", "valu_per_call", "waves", "issue",
+                                                     "lane/pair")]
     for short in ("fwd3d_kernel", "back3d_kernel", "rec_kernel"):
         disp = {}
         for r in rows:
@@ -209,7 +217,10 @@ def digest_valu(args):
         v = sum(d.get("SQ_INSTS_VALU", 0.0) for d in disp.values()) / n
         w = sum(d.get("SQ_WAVES", 0.0) for d in disp.values()) / n
         issue = v * 4.0 / (1024 * 2.4e9 * t) if t > 0 else 0.0
-        lines.append("%-16s %5d %12.4f %16.4g %12.4g %9.3f" % (short, n, t * 1e3, v, w, issue))
+        # the record kernel runs once per direction and chunk: half its
+        # launches cover the pairs once
+        per_pair = 64.0 * v * (n / 2 if short == "rec_kernel" else n) / args.nnz if args.nnz else float("nan")
+        lines.append("%-16s %5d %12.4f %16.4g %12.4g %9.3f %10.2f" % (short, n, t * 1e3, v, w, issue, per_pair))
     _write(args.out, lines)
 
 

@@ -95,15 +95,18 @@ class Server:
 
     def footprint(self, r: Request, batch: int) -> int:
         """Device bytes a launch of `batch` such requests holds while it runs:
-        outputs and the library workspace (the inputs are already resident)."""
+        outputs, the library workspace and, for batch > 1, the stacked copy of
+        the inputs (each input itself is already resident)."""
         A = self.plan(r.key, r.geometry)
         es = 8 if self.precision == "fp64" else 4
         if r.kind == "forward":
-            return A.workspace_bytes(batch) + batch * A.n_rays * es
+            stacked = batch * A.n_vox * es if batch > 1 else 0
+            return A.workspace_bytes(batch) + batch * A.n_rays * es + stacked
         n = C_int64()
         _lib.check(_lib.lib().sm_solver_workspace_size(A._plan, _lib.SM_SOLVER_CGLS, batch, n.ref()),
                    "sm_solver_workspace_size")
-        return n.value + batch * (A.n_vox * es + (r.iters + 1) * 8)
+        stacked = batch * A.n_rays * es if batch > 1 else 0
+        return n.value + batch * (A.n_vox * es + (r.iters + 1) * 8) + stacked
 
     # ---------------------------------------------------------------- launch
     def _launch(self, reqs: List[Request], slot: int, footprint: int, now: float) -> _Launch:

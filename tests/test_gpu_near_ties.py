@@ -1,0 +1,107 @@
+"""Row planes that meet voxel faces exactly, or within one FP32 rounding step,
+away from z = 0 (Sec. III-C: the sign coefficients C decide, per sub-volume,
+on which side of a row plane a voxel face lies).
+
+FP32 plans classify planes against faces in FP32 (the plane and face splits),
+FP64 plans in FP64.  Here the detector is shifted vertically so that in view
+0 the row plane r passes exactly through the edge, or a corner, of voxel
+column (ix, iy) at the height of face j != 0, or one FP32 unit in the last
+place above or below it: then the split can put the plane on either side of
+the face.  Both operators must still match the FP64 oracle's matrix at the
+parity bars, globally and element by element on the voxels sharing that face
+and the rays on both sides of that plane (a misclassified plane may only move
+a volume of rounding size).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2511_12235_amd import workloads as wl
+from paper_2511_12235_amd.projector import SystemMatrix
+
+from _errlog import note, record
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+S_, D_ = 30.0, 20.0
+N = (8, 8, 8)
+DET, DPITCH = (12, 10), (1.2, 1.2)
+
+# (view-0 angle, pixel (ix, iy), face j, plane r, which depth of the pixel)
+CASES = {
+    "axis_near_edge": (0.0, (5, 3), 5, 6, "near"),
+    "axis_far_edge": (0.0, (5, 3), 6, 6, "far"),
+    "oblique_near_corner_below_0": (0.3, (2, 6), 2, 3, "near"),
+    "oblique_far_corner": (0.3, (6, 2), 6, 7, "far"),
+}
+
+
+def _say(*msg):
+    print("[case]", *msg, flush=True)
+
+
+def _t(a, prec):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, torch.float64 if prec == "fp64" else torch.float32)
+
+
+def tie_geometry(name, nudge):
+    """Geometry whose row plane r meets face z_j at the chosen corner depth of
+    pixel (ix, iy) in view 0; `nudge` moves the plane by that many FP32 units
+    in the last place of its detector coordinate."""
+    phi0, (ix, iy), j, r, which = CASES[name]
+    a = b = c = 1.0
+    x0, y0, z0 = -N[0] * a / 2, -N[1] * b / 2, -N[2] * c / 2
+    cp, sp = np.cos(phi0), np.sin(phi0)
+    depths = [S_ - ((x0 + (ix + dx) * a) * cp + (y0 + (iy + dy) * b) * sp) for dx in (0, 1) for dy in (0, 1)]
+    l_tie = min(depths) if which == "near" else max(depths)
+    z_j = z0 + j * c
+    v_r = z_j * (S_ + D_) / l_tie * (1.0 + nudge * 2.0 ** -24)
+    det_z0 = v_r - r * DPITCH[1]
+    phi = np.array([phi0, phi0 + 2.1, phi0 + 4.2])
+    g = wl.make_geometry(3, N, (a, b, c), 3, S_, D_, DET, DPITCH, phi=phi,
+                         det_corner=(-DET[0] * DPITCH[0] / 2, det_z0))
+    return g, (ix, iy, j, r)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("nudge", [-1, 0, 1])
+@pytest.mark.parametrize("name", list(CASES))
+def test_plane_through_face(name, nudge, prec):
+    g, (ix, iy, j, r) = tie_geometry(name, nudge)
+    _say("near tie", name, "nudge", nudge, prec)
+    W = O.matrix(g)
+    A = SystemMatrix(g, prec, device=DEV)
+    tag = "%s nudge %+d %s" % (name, nudge, prec)
+    # the plane passes through the face: some ray in view 0, rows r - 1 or r,
+    # meets the voxels on both sides of face j
+    vox = [((j - 1) * g.ny + iy) * g.nx + ix, (j * g.ny + iy) * g.nx + ix]
+    rows_ = [(0 * g.det_nz + rr) * g.det_ny + k for rr in (r - 1, r) if 0 <= rr < g.det_nz for k in range(g.det_ny)]
+    assert W[rows_][:, vox].nnz > 0, "the tie voxels are not in the beam"
+    # whole operators
+    x = wl.ellipse_phantom(g, 4, seed=3) + wl.uniform(g.vol_shape, 4, 0.0, 0.01)
+    y = wl.uniform(g.sino_shape, 5)
+    yg = A.forward(_t(x, prec)).double().cpu().numpy().ravel()
+    xg = A.back(_t(y, prec)).double().cpu().numpy().ravel()
+    rel, _ = record("near tie forward, " + tag, yg, W @ x.ravel(), TOL[prec])
+    assert rel <= TOL[prec]
+    rel, _ = record("near tie adjoint, " + tag, xg, W.T @ y.ravel(), TOL[prec])
+    assert rel <= TOL[prec]
+    # element by element: the two voxels sharing face j, all rays (columns of
+    # W); the rays on both sides of plane r, all voxels (rows of W)
+    vol = g.a * g.b * g.c
+    e = np.zeros(g.n_vox)
+    e[vox] = 1.0
+    col = W @ e
+    cg = A.forward(_t(e.reshape(g.vol_shape), prec)).double().cpu().numpy().ravel()
+    err_c = float(np.abs(cg - col).max()) / vol
+    f = np.zeros(g.n_rays)
+    f[rows_] = 1.0
+    row = W.T @ f
+    rg = A.back(_t(f.reshape(g.sino_shape), prec)).double().cpu().numpy().ravel()
+    err_r = float(np.abs(rg - row).max()) / vol
+    note("near tie, max |error| / voxel volume, " + tag, max(err_c, err_r), max(err_c, err_r), 2, TOL[prec],
+         kind="max_abs_vol")
+    assert err_c <= TOL[prec] and err_r <= TOL[prec], (err_c, err_r)

@@ -44,7 +44,18 @@ def test_results_equal_alone_and_in_the_mix():
     budget = int(2.5 * biggest)
     srv = serve.Server(DEV, hbm_budget=budget, slots=4, keep_results=True)
     srv.plans = probe.plans
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated(DEV)
+    torch.cuda.reset_peak_memory_stats(DEV)
     srv.run(reqs)
+    torch.cuda.synchronize()
+    # device memory the run allocated beyond what it keeps (the results and
+    # the CG histories of finished launches) stays within the admission budget
+    peak = torch.cuda.max_memory_allocated(DEV) - base
+    kept = sum(r.result.numel() * r.result.element_size() for r in reqs) + 8 * sum(
+        (r.iters + 1) for r in reqs if r.kind == "cg")
+    print("[serve] peak allocation %d bytes, budget %d, kept %d" % (peak, budget, kept), flush=True)
+    assert peak <= budget + kept + (4 << 20)
     alone = [dataclasses.replace(r, result=None) for r in reqs]
     srv.run_sequential(alone)
     for a, b in zip(reqs, alone):
