@@ -52,8 +52,24 @@ ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # pair's multiply-add (2 flop).
 FLOP_PER_PAIR = 23
 KERNEL_SYMBOL = {"forward": "fwd3d_kernel", "adjoint": "back3d_kernel",
-                 "records": "rec_kernel", "prefix": "prefix_kernel",
+                 "records": "rec_kernel", "prefix": "columns_kernel",
                  "transpose": "from_columns_kernel"}
+KERNEL_SYMBOL_2D = {"forward": "fwd2d_kernel", "adjoint": "back2d_kernel"}
+
+
+def _geometry(config):
+    from paper_2511_12235_amd import workloads as wl
+    return CONFIGS[config](wl)
+
+
+CONFIGS = {"c1": lambda wl: wl.c1_fan2d(), "c2": lambda wl: wl.c2_cone128(), "c3": lambda wl: wl.c3_cone256(),
+           "c4": lambda wl: wl.c4_batch128(), "fan256": lambda wl: wl.serving_geometry("2d256")}
+
+
+def _describe(g):
+    if g.dim == 2:
+        return "fan-beam %d^2 pixels, %d views, %d detector cells" % (g.nx, g.n_p, g.det_ny)
+    return "cone-beam %d^3 voxels, %d views, %dx%d detector" % (g.nx, g.n_p, g.det_ny, g.det_nz)
 
 
 def parse():
@@ -62,7 +78,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--config", default="c3", choices=["c2", "c3"])
+    ap.add_argument("--config", default="c3", choices=sorted(CONFIGS),
+                    help="c3: the 256^3 headline workload; c2: 128^3, 180 views; c4: 128^3, 120 views; "
+                         "c1: 2D fan 64^2, 90 views; fan256: 2D fan 256^2, 360 views (serving size)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stored", action="store_true",
                     help="time the stored-W mode beside the matrix-free operators instead")
@@ -105,7 +123,7 @@ def sources_digest():
 
 def counters_file(config, precision, kernel):
     return os.path.join(ROOT, "profiles", "%s_%s_%s_hbm_counters.txt"
-                        % (kernel, "cone256" if config == "c3" else "cone128", precision))
+                        % (kernel, {"c3": "cone256", "c2": "cone128"}.get(config, config), precision))
 
 
 def read_summary(path):
@@ -271,7 +289,7 @@ def stored_bench(args):
     from paper_2511_12235_amd import workloads as wl
     from paper_2511_12235_amd.projector import StoredMatrix, SystemMatrix
 
-    g = wl.c3_cone256() if args.config == "c3" else wl.c2_cone128()
+    g = _geometry(args.config)
     dev = torch.device("cuda:0")
     A = SystemMatrix(g, args.precision, device=dev)
     dt = A.dtype
@@ -307,8 +325,7 @@ def stored_bench(args):
     b_fwd = nnz * (4 + vb) + 8 * (A.n_rays + 1) + vb * (A.n_vox + A.n_rays)
     b_back = nnz * (4 + vb) + 8 * (A.n_vox + 1) + vb * (A.n_vox + A.n_rays)
     rel = lambda a, b: float(torch.linalg.norm((a - b).double()) / torch.linalg.norm(b.double()))
-    res = {"mode": "stored-W vs matrix-free", "config": {"workload": "cone-beam %d^3, %d views, %dx%d detector"
-                                                          % (g.nx, g.n_p, g.det_ny, g.det_nz)},
+    res = {"mode": "stored-W vs matrix-free", "config": {"workload": _describe(g)},
            "precision": args.precision, "nnz": nnz, "stored_bytes": 2 * nnz * (4 + vb),
            "build_s": build_s,
            "ms_forward": {"stored": ms_sf, "matrix_free": ms_mf},
@@ -329,7 +346,7 @@ def line_bench(args):
     from paper_2511_12235_amd import workloads as wl
     from paper_2511_12235_amd.projector import SystemMatrix
 
-    g = wl.c3_cone256() if args.config == "c3" else wl.c2_cone128()
+    g = _geometry(args.config)
     dev = torch.device("cuda:0")
     A = SystemMatrix(g, args.precision, device=dev)
     dt = A.dtype
@@ -363,8 +380,7 @@ def line_bench(args):
             print("line k=%d %s: forward %.2f ms, adjoint %.2f ms" % (k, w, mf, mb), file=sys.stderr, flush=True)
     area = {"ms_forward": timed(lambda: A.forward(x, ws=ws), reps),
             "ms_adjoint": timed(lambda: A.back(yin, ws=ws), reps)}
-    res = {"mode": "line-based vs exact", "config": {"workload": "cone-beam %d^3, %d views, %dx%d detector"
-                                                     % (g.nx, g.n_p, g.det_ny, g.det_nz)},
+    res = {"mode": "line-based vs exact", "config": {"workload": _describe(g)},
            "precision": args.precision, "line": rows, "exact": area}
     print(json.dumps(res), flush=True)
 
@@ -395,7 +411,7 @@ def main():
     from paper_2511_12235_amd import workloads as wl
     from paper_2511_12235_amd.projector import SystemMatrix
 
-    g = wl.c3_cone256() if args.config == "c3" else wl.c2_cone128()
+    g = _geometry(args.config)
     dev = torch.device("cuda:0")
     A = SystemMatrix(g, args.precision, device=dev)
     dt = A.dtype
@@ -463,12 +479,15 @@ def main():
     ms_launch = ms / max(launches, 1)
     pairs_per_launch = nnz * B * args.steps / max(launches, 1) if dom in ("forward", "adjoint") else 0.0
     achieved = FLOP_PER_PAIR * pairs_per_launch / (ms_launch / 1e3) / 1e12 if ms_launch > 0 else 0.0
+    symbol = (KERNEL_SYMBOL_2D if g.dim == 2 else KERNEL_SYMBOL)[dom]
     # the counter summaries were taken on single-volume launches
-    traffic = traffic_per_launch(args.config, args.precision, KERNEL_SYMBOL[dom]) if B == 1 else None
+    traffic = traffic_per_launch(args.config, args.precision, symbol) if B == 1 and g.dim == 3 else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic,
-                "kernel": KERNEL_SYMBOL[dom], "ms_per_launch": ms_launch,
+                "kernel": symbol, "ms_per_launch": ms_launch,
                 "pairs_per_launch": pairs_per_launch, "flop_per_pair": FLOP_PER_PAIR}
+    if g.dim == 2:  # the 23 flop per pair count is the 3D K evaluation's
+        roofline = {"kernel": symbol, "ms_per_launch": ms_launch, "pairs_per_launch": pairs_per_launch}
 
     res = {
         "metric": "Wx+W^Ty voxel-detector pairs/s at 256^3 (% HBM roofline); p50/p99 solve latency",
@@ -483,8 +502,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "cone-beam %d^3 voxels, %d views, %dx%d detector, forward + adjoint"
-                               % (g.nx, g.n_p, g.det_ny, g.det_nz) + (", %d volumes per call" % B if B > 1 else ""),
+        "config": {"workload": _describe(g) + ", forward + adjoint" + (", %d volumes per call" % B if B > 1 else ""),
                    "nnz_pairs": nnz, "ms_forward": float(np.mean(t_f)) * 1e3,
                    "ms_adjoint": float(np.mean(t_b)) * 1e3, "nnz_count_s": count_s,
                    "wall_s": wall,
@@ -494,7 +512,7 @@ def main():
                                if args.keep_records else "rebuilt in every call")},
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and g.dim == 3:
         res["cpu_baseline"] = cpu_baseline(g, args.cpu_views)
     print(json.dumps(res), flush=True)
 

@@ -343,7 +343,7 @@ typedef enum {
     SM_KERNEL_RECORDS = 0,   /* strip polygons and chord tables (Sec. III-B) */
     SM_KERNEL_FORWARD = 1,   /* y = W x accumulation (Sec. III-C) */
     SM_KERNEL_ADJOINT = 2,   /* x = W^T y accumulation */
-    SM_KERNEL_PREFIX = 3,    /* column prefix sums of the forward input */
+    SM_KERNEL_PREFIX = 3,    /* the forward's input pass: voxel columns (and max|x|) */
     SM_KERNEL_TRANSPOSE = 4, /* adjoint output to the caller's layout */
     SM_KERNEL_COUNT = 5
 } sm_kernel;

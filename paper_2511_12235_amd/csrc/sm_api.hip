@@ -126,12 +126,12 @@ sm_status check_plan_device(const sm_plan *p) { return check_device(p); }
 namespace smk {
 
 // Volume buffers of one call, behind the records of a chunk: the forward's
-// FP64 prefix sums and max |x| per batch element, the adjoint's `groups`
+// voxel columns and max |x| per batch element, the adjoint's `groups`
 // partial volumes.
 int64_t fwd_volume_bytes(const sm_plan *p, int64_t batch)
 {
-    const int64_t npix = (int64_t)p->G.nx * p->G.ny;
-    return smk::align256(npix * batch * (int64_t)(p->G.nz + 1) * (int64_t)sizeof(double)) +
+    const int64_t es = p->prec == SM_FP64 ? 8 : 4;
+    return smk::align256((int64_t)p->G.nx * p->G.ny * batch * p->G.nz * es) +
            smk::align256(batch * (int64_t)sizeof(unsigned));
 }
 
@@ -165,12 +165,11 @@ hipError_t run_forward3d(const sm_plan *p, const smk::RecLayout &RL, const void 
                          int batch, void *recws, void *vol, hipStream_t st)
 {
     const bool f64 = p->prec == SM_FP64;
-    double *P = (double *)vol;
-    const int64_t npix = (int64_t)p->G.nx * p->G.ny;
-    unsigned *xmax = (unsigned *)((char *)P + smk::align256(npix * batch * (int64_t)(p->G.nz + 1) *
-                                                            (int64_t)sizeof(double)));
+    void *X = vol;
+    unsigned *xmax = (unsigned *)((char *)vol + smk::align256((int64_t)p->G.nx * p->G.ny * batch *
+                                                              p->G.nz * (f64 ? 8 : 4)));
     int q = tm_begin(p, SM_KERNEL_PREFIX, st);
-    hipError_t e = smk::launch_prefix_columns(x, P, xmax, f64, batch, p->G.nz, p->G.ny, p->G.nx, st);
+    hipError_t e = smk::launch_to_columns(x, X, xmax, f64, batch, p->G.nz, p->G.ny, p->G.nx, st);
     tm_end(p, q, st);
     for (int v0 = 0; v0 < p->G.n_p && e == hipSuccess; v0 += RL.views) {
         const int nvc = p->G.n_p - v0 < RL.views ? p->G.n_p - v0 : RL.views;
@@ -184,7 +183,7 @@ hipError_t run_forward3d(const sm_plan *p, const smk::RecLayout &RL, const void 
             if (e != hipSuccess) break;
         }
         q = tm_begin(p, SM_KERNEL_FORWARD, st);
-        e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, rws, P, xmax, y, batch, st);
+        e = smk::launch_fwd3d(p->G, p->L, RL, f64, v0, nvc, rws, X, xmax, y, batch, st);
         tm_end(p, q, st);
     }
     return e;

@@ -18,9 +18,110 @@
 // A (tau lbar - za) at za; only planes straddling a face need the chord
 // table.  Chunks of views add into the z-contiguous workspace in a fixed
 // order, which is transposed to the caller's layout afterwards.
+
 #include "sm_internal.h"
 
 namespace smk {
+
+// Stage view `view`'s detector columns kmin .. kmax (pc of them, all rows,
+// zero rows at -1 and nv) and the strip records of the tile's pixels, slot
+// (p, k - k0(p)) at rtab + slot * RS bytes; a slot without a record gets
+// n = 0.
+template <typename T, int NBAT, int TX, int TY, size_t RS>
+__device__ __forceinline__ void stage_view(const DevGeom &G, const RecLayout &RL, const StripAxis &ax,
+                                           int vl, int view, int ix0, int iy0, int kmin, int kmax,
+                                           const Rec<T> *__restrict__ recs, const int *__restrict__ sj0,
+                                           const int *__restrict__ soff, const int2 *__restrict__ pixk,
+                                           const T *__restrict__ y, int b0, int pcols, int rspan,
+                                           unsigned char *rtab, T *patch)
+{
+    constexpr int TP = TX * TY;
+    constexpr int RCH = (int)(sizeof(Rec<T>) / 16);  // 16-byte chunks per record
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    const int nv = G.nv, rowstride = nv + 2, npix = G.nx * G.ny;
+    const int pc = kmax - kmin + 1;
+    // y[view][:, kmin..kmax] (a single volume: one thread per detector row, its
+    // pc values side by side; batches: consecutive threads on consecutive columns)
+    for (int bb = 0; bb < NBAT; ++bb) {
+        const T *src = y + ((size_t)(b0 + bb) * G.n_p + view) * nv * G.nu + kmin;
+        T *dst = patch + (size_t)bb * pcols * rowstride + 1;
+        if constexpr (NBAT == 1) {
+            for (int row = tid; row < nv; row += nthr) {
+                const T *s = src + (size_t)row * G.nu;
+                T *d = dst + row;
+                for (int col = 0; col < pc; ++col) d[col * rowstride] = s[col];
+            }
+        } else {
+            const float inv_pc = 1.0f / (float)pc;
+            for (int q = tid; q < pc * nv; q += nthr) {
+                const int row = (int)(((float)q + 0.5f) * inv_pc);
+                const int col = q - row * pc;
+                dst[col * rowstride + row] = src[(size_t)row * G.nu + col];
+            }
+        }
+        for (int col = tid; col < pc; col += nthr) {
+            dst[col * rowstride - 1] = T(0);
+            dst[col * rowstride + nv] = T(0);
+        }
+    }
+    // strip records: a single volume copies a whole record per thread (one
+    // slot lookup, its registers are free); batches, which hold more sums,
+    // copy one 16-byte chunk per thread
+    constexpr int CPT = NBAT == 1 ? RCH : 1;  // chunks per thread
+    constexpr int TPS = RCH / CPT;            // threads per slot
+    const float inv_rspan = 1.0f / (float)rspan;
+    for (int q = tid; q < TP * rspan * TPS; q += nthr) {
+        const int pk = q / TPS, ch0 = (q - pk * TPS) * CPT;   // TPS is a constant
+        const int p = (int)(((float)pk + 0.5f) * inv_rspan);  // exact for pk < 16 rspan, rspan <= 2048
+        const int kk = pk - p * rspan;
+        const int ix = ix0 + p % TX, iy = iy0 + p / TX;
+        uint4 *dst = reinterpret_cast<uint4 *>(rtab + (size_t)(p * rspan + kk) * RS);
+        int pos = -1;
+        int64_t strip = 0;
+        if (ix < G.nx && iy < G.ny) {
+            const int2 kr = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
+            const int k = kr.x + kk;
+            if (k <= kr.y && k >= kmin && k <= kmax) {
+                strip = (int64_t)vl * G.nu + k;
+                pos = strip_position(ax.major_x, ix, iy, sj0 + strip * RL.n_major_max,
+                                     soff + strip * (RL.n_major_max + 1));
+            }
+        }
+        if (pos >= 0) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(recs + strip * RL.cap + pos);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) dst[ch0 + c] = src[ch0 + c];
+        } else if (ch0 == 0) {
+            dst[0] = make_uint4(0u, 0u, 0u, 0u);  // lc = 0, n = 0
+        }
+    }
+}
+
+// Detector columns the tile's pixels meet in view vl (from the record pass):
+// false when none; kmax is clipped so that kmax - kmin < pcols.
+template <int TX, int TY>
+__device__ __forceinline__ bool tile_columns(const DevGeom &G, const int2 *__restrict__ pixk, int vl,
+                                             int ix0, int iy0, int pcols, int &kmin, int &kmax)
+{
+    constexpr int TP = TX * TY;
+    const int npix = G.nx * G.ny;
+    kmin = 1 << 30;
+    kmax = -1;
+#pragma unroll
+    for (int p = 0; p < TP; ++p) {
+        const int ix = ix0 + p % TX, iy = iy0 + p / TX;
+        if (ix < G.nx && iy < G.ny) {
+            const int2 q = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
+            if (q.y >= q.x) {
+                kmin = min(kmin, q.x);
+                kmax = max(kmax, q.y);
+            }
+        }
+    }
+    if (kmax < kmin) return false;
+    if (kmax - kmin + 1 > pcols) kmax = kmin + pcols - 1;  // pcols bounds every tile's span
+    return true;
+}
 
 template <typename T, int NBAT, int TX, int TY>
 __global__ void __launch_bounds__(1024)
@@ -30,7 +131,6 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
               int b0, int pcols, int rspan, int first, int groups)
 {
     constexpr int TP = TX * TY;
-    constexpr int RCH = (int)(sizeof(Rec<T>) / 16);  // 16-byte chunks per record
     extern __shared__ __align__(16) unsigned char smem[];
     const int nthr = blockDim.x, tid = threadIdx.x;
     const int nz = G.nz, nv = G.nv;
@@ -72,6 +172,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
     const double zb = G.z0 + (double)(iz + 1) * G.c;
     const T cT = T(G.c);
     const T v0dv = T(G.v0 / G.dv);
+    const double dtau = G.dv / G.D;  // spacing of the plane slopes
 
     T acc[TP][NBAT];
 #pragma unroll
@@ -83,80 +184,12 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
         const int view = v0 + vl;
         const double2 cs = G.trig[view];
         const StripAxis ax = strip_axis(G, cs.x, cs.y);
-        // detector columns the tile's pixels meet (from the record pass)
-        int kmin = 1 << 30, kmax = -1;
-#pragma unroll
-        for (int p = 0; p < TP; ++p) {
-            const int ix = ix0 + p % TX, iy = iy0 + p / TX;
-            if (ix < G.nx && iy < G.ny) {
-                const int2 q = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
-                if (q.y >= q.x) {
-                    kmin = min(kmin, q.x);
-                    kmax = max(kmax, q.y);
-                }
-            }
-        }
-        if (kmax < kmin) continue;
-        if (kmax - kmin + 1 > pcols) kmax = kmin + pcols - 1;  // pcols bounds every tile's span
-        const int pc = kmax - kmin + 1;
+        int kmin, kmax;
+        if (!tile_columns<TX, TY>(G, pixk, vl, ix0, iy0, pcols, kmin, kmax)) continue;
         __syncthreads();  // the previous view's patch and records are consumed
-        // --- stage y[view][:, kmin..kmax] with zero rows at -1 and nv
-        // (a single volume: one thread per detector row, its pc values side by
-        // side; batches: consecutive threads on consecutive columns)
-        for (int bb = 0; bb < NBAT; ++bb) {
-            const T *src = y + ((size_t)(b0 + bb) * G.n_p + view) * nv * G.nu + kmin;
-            T *dst = patch + (size_t)bb * pcols * rowstride + 1;
-            if constexpr (NBAT == 1) {
-                for (int row = tid; row < nv; row += nthr) {
-                    const T *s = src + (size_t)row * G.nu;
-                    T *d = dst + row;
-                    for (int col = 0; col < pc; ++col) d[col * rowstride] = s[col];
-                }
-            } else {
-                const float inv_pc = 1.0f / (float)pc;
-                for (int q = tid; q < pc * nv; q += nthr) {
-                    const int row = (int)(((float)q + 0.5f) * inv_pc);
-                    const int col = q - row * pc;
-                    dst[col * rowstride + row] = src[(size_t)row * G.nu + col];
-                }
-            }
-            for (int col = tid; col < pc; col += nthr) {
-                dst[col * rowstride - 1] = T(0);
-                dst[col * rowstride + nv] = T(0);
-            }
-        }
-        // --- stage the strip records of the tile's pixels in slot (p, k - k0(p));
-        // a slot without a record gets n = 0.  A single volume copies a whole
-        // record per thread (one slot lookup, its registers are free); batches,
-        // which hold more sums, copy one 16-byte chunk per thread.
-        constexpr int CPT = NBAT == 1 ? RCH : 1;  // chunks per thread
-        constexpr int TPS = RCH / CPT;            // threads per slot
-        const float inv_rspan = 1.0f / (float)rspan;
-        for (int q = tid; q < TP * rspan * TPS; q += nthr) {
-            const int pk = q / TPS, ch0 = (q - pk * TPS) * CPT;   // TPS is a constant
-            const int p = (int)(((float)pk + 0.5f) * inv_rspan);  // exact for pk < 16 rspan, rspan <= 2048
-            const int kk = pk - p * rspan;
-            const int ix = ix0 + p % TX, iy = iy0 + p / TX;
-            uint4 *dst = reinterpret_cast<uint4 *>(rtab + p * rspan + kk);
-            int pos = -1;
-            int64_t strip = 0;
-            if (ix < G.nx && iy < G.ny) {
-                const int2 kr = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
-                const int k = kr.x + kk;
-                if (k <= kr.y && k >= kmin && k <= kmax) {
-                    strip = (int64_t)vl * G.nu + k;
-                    pos = strip_position(ax.major_x, ix, iy, sj0 + strip * RL.n_major_max,
-                                         soff + strip * (RL.n_major_max + 1));
-                }
-            }
-            if (pos >= 0) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(recs + strip * RL.cap + pos);
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) dst[ch0 + c] = src[ch0 + c];
-            } else if (ch0 == 0) {
-                dst[0] = make_uint4(0u, 0u, 0u, 0u);  // lc = 0, n = 0
-            }
-        }
+        stage_view<T, NBAT, TX, TY, sizeof(Rec<T>)>(G, RL, ax, vl, view, ix0, iy0, kmin, kmax, recs, sj0,
+                                                    soff, pixk, y, b0, pcols, rspan,
+                                                    reinterpret_cast<unsigned char *>(rtab), patch);
         __syncthreads();
         if (!active) continue;
         // Pixels in a loop unrolled by 8: the current pixel's sums are acc[0];
@@ -183,8 +216,8 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
                 const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
                 const T *Y = patch + (size_t)(k - kmin) * rowstride + 1;  // Y[-1] .. Y[nv]
                 T sum[NBAT];
-                adj_terms<T, NBAT>(S, R.lc, R.lbo, R.kLo, R.kHi, ptau, ptf, pinv, za, zb, v0dv, nv,
-                                   cT, Y, (size_t)pcols * rowstride, sum);
+                adj_terms<T, NBAT>(S, R.lc, R.lbo, R.kLo, R.kHi, ptau, dtau, ptf, pinv, za, zb, v0dv,
+                                   nv, cT, Y, (size_t)pcols * rowstride, sum);
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) cur[b] += sum[b];
             }

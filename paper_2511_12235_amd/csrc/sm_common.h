@@ -459,11 +459,12 @@ __host__ __device__ inline void plane_extent(T tau, T Llo, T Lhi, T &lo, T &hi)
 // The part of G_p of one plane for one strip record that needs no chord
 // table: the linear volume at face f = fa - 1 (the first voxel not wholly
 // below the plane).  Faces fa .. je are straddled (empty when je < fa); their
-// terms come from straddle_term.
+// terms come from straddle_term.  Xc[b] is the voxel column (x_0 .. x_{nz-1})
+// of batch element b.
 template <typename T, int NBAT>
 __host__ __device__ inline void plane_lin(const DevGeom &G, const StripTab<T> &S, double lbar,
                                           T Llo, T Lhi, double tau, T tauf, T inv_c, T z0c,
-                                          const double *const (&Pc)[NBAT], int &f_out, int &fa_out,
+                                          const T *const (&Xc)[NBAT], int &f_out, int &fa_out,
                                           int &je_out, T (&gs)[NBAT])
 {
     const int nz = G.nz;
@@ -480,7 +481,7 @@ __host__ __device__ inline void plane_lin(const DevGeom &G, const StripTab<T> &S
     if (fa >= 1 && fa <= nz) {  // face f wholly below the plane: linear volume
         const T K = S.A * T(tau * lbar - (G.z0 + (double)f * G.c));
 #pragma unroll
-        for (int b = 0; b < NBAT; ++b) gs[b] = K * T(Pc[b][f + 1] - Pc[b][f]);
+        for (int b = 0; b < NBAT; ++b) gs[b] = K * Xc[b][f];  // f = fa - 1 < nz
     }
 }
 
@@ -488,15 +489,14 @@ __host__ __device__ inline void plane_lin(const DevGeom &G, const StripTab<T> &S
 template <typename T, int NBAT>
 __host__ __device__ inline void straddle_term(const DevGeom &G, const StripTab<T> &S, double lc,
                                               double tau, T tauf, T invt, int j,
-                                              const double *const (&Pc)[NBAT], T (&out)[NBAT])
+                                              const T *const (&Xc)[NBAT], T (&out)[NBAT])
 {
     const int nz = G.nz;
     const T K = K_cut<T>(S, tauf, invt, T(tau * lc - (G.z0 + (double)j * G.c)));
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) {
-        const double P0 = Pc[b][j];
-        const T xj = j < nz ? T(Pc[b][j + 1] - P0) : T(0);
-        const T xm = j >= 1 ? T(P0 - Pc[b][j - 1]) : T(0);
+        const T xj = j < nz ? Xc[b][j] : T(0);
+        const T xm = j >= 1 ? Xc[b][j - 1] : T(0);
         out[b] = K * (xj - xm);
     }
 }
@@ -505,14 +505,14 @@ __host__ __device__ inline void straddle_term(const DevGeom &G, const StripTab<T
 template <typename T, int NBAT>
 __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, double lc,
                                         double lbar, T Llo, T Lhi, double tau, T tauf, T invt,
-                                        T inv_c, T z0c, const double *const (&Pc)[NBAT], int &f_out,
+                                        T inv_c, T z0c, const T *const (&Xc)[NBAT], int &f_out,
                                         T (&gs)[NBAT])
 {
     int fa, je;
-    plane_lin<T, NBAT>(G, S, lbar, Llo, Lhi, tau, tauf, inv_c, z0c, Pc, f_out, fa, je, gs);
+    plane_lin<T, NBAT>(G, S, lbar, Llo, Lhi, tau, tauf, inv_c, z0c, Xc, f_out, fa, je, gs);
     for (int j = fa; j <= je; ++j) {
         T t[NBAT];
-        straddle_term<T, NBAT>(G, S, lc, tau, tauf, invt, j, Pc, t);
+        straddle_term<T, NBAT>(G, S, lc, tau, tauf, invt, j, Xc, t);
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) gs[b] += t[b];
     }
@@ -524,11 +524,20 @@ __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, 
 // above za that reach below zb.  Planes pha .. paa - 1 straddle za and
 // phb .. pab - 1 straddle zb (adj_straddle gives their terms).
 // Y[b * ystride + q] holds y[q] of batch element b for q in [-1, nv];
-// ptau / ptf / pinv are the plane slopes in FP64, in T and their inverses.
+// ptau holds the plane slopes in FP64, dtau = dv / D their spacing.
+//
+// The linear volumes are K_q = A (tau_q lbar - za) = A (alpha + (q - a) beta)
+// for q = a .. e - 1 (a = paa, e = pab), with A alpha = K_a and beta = dtau
+// lbar.  FP64 plans sum them by parts,
+//     sum_q K_q (y[q-1] - y[q]) = A alpha (y[a-1] - y[e-1])
+//                                 + A beta sum_{q=a}^{e-2} (y[q] - y[e-1]),
+// so that their loop only adds row differences (one FP64 product per record
+// instead of one per plane); FP32 plans evaluate K_q per plane, which
+// measured faster in FP32 (40.9 against 43.7 ms per call at 256^3).
 template <typename T, int NBAT>
 __host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T lbo, T kLo, T kHi,
-                                        const double *ptau, double za, double zb, T v0dv, int nv,
-                                        T cT, const T *Y, size_t ystride, int &pha, int &paa,
+                                        const double *ptau, double dtau, double za, double zb, T v0dv,
+                                        int nv, T cT, const T *Y, size_t ystride, int &pha, int &paa,
                                         int &phb, int &pab, T (&sum)[NBAT])
 {
     const double lbar = lc + (double)lbo;  // area-weighted mean depth
@@ -537,10 +546,23 @@ __host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T lbo, 
     const T cA = cT * S.A;
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) sum[b] = cA * Y[b * ystride + pab - 1];
-    for (int q = paa; q < pab; ++q) {
-        const T K = S.A * T(ptau[q] * lbar - za);
+    if constexpr (sizeof(T) == 4) {
+        for (int q = paa; q < pab; ++q) {
+            const T K = S.A * T(ptau[q] * lbar - za);
 #pragma unroll
-        for (int b = 0; b < NBAT; ++b) sum[b] += K * (Y[b * ystride + q - 1] - Y[b * ystride + q]);
+            for (int b = 0; b < NBAT; ++b) sum[b] += K * (Y[b * ystride + q - 1] - Y[b * ystride + q]);
+        }
+    } else if (pab > paa) {
+        const T alpha = S.A * T(ptau[paa] * lbar - za);
+        const T beta = S.A * T(dtau * lbar);
+#pragma unroll
+        for (int b = 0; b < NBAT; ++b) {
+            const T *Yb = Y + b * ystride;
+            const T ye = Yb[pab - 1];
+            T d = T(0);
+            for (int q = paa; q < pab - 1; ++q) d += Yb[q] - ye;
+            sum[b] += alpha * (Yb[paa - 1] - ye) + beta * d;
+        }
     }
 }
 
@@ -567,13 +589,13 @@ __host__ __device__ inline int adj_straddle(int t, int na, int pha, int phb, con
 // adjoint: sum_q (K_q(za) - K_q(zb)) (y[q-1] - y[q]) with y[-1] = y[nv] = 0.
 template <typename T, int NBAT>
 __host__ __device__ inline void adj_terms(const StripTab<T> &S, double lc, T lbo, T kLo, T kHi,
-                                          const double *ptau, const T *ptf, const T *pinv,
-                                          double za, double zb, T v0dv, int nv, T cT,
+                                          const double *ptau, double dtau, const T *ptf,
+                                          const T *pinv, double za, double zb, T v0dv, int nv, T cT,
                                           const T *Y, size_t ystride, T (&sum)[NBAT])
 {
     int pha, paa, phb, pab;
-    adj_lin<T, NBAT>(S, lc, lbo, kLo, kHi, ptau, za, zb, v0dv, nv, cT, Y, ystride, pha, paa, phb,
-                     pab, sum);
+    adj_lin<T, NBAT>(S, lc, lbo, kLo, kHi, ptau, dtau, za, zb, v0dv, nv, cT, Y, ystride, pha, paa,
+                     phb, pab, sum);
     const int na = max(paa - pha, 0);
     const int nb = max(pab - phb, 0);
     for (int t = 0; t < na + nb; ++t) {

@@ -13,8 +13,10 @@
 // z_f up, K_p(z) the volume of the strip column above z and below plane p
 // (sm_common.h).  Face z_f lies wholly below the plane, so K_p(z_f) is the
 // linear volume A (tau lbar - z_f); faces the plane straddles need the chord
-// table; faces wholly above it add nothing.  Voxel sums come from FP64 prefix
-// sums along z, so c A (V_{r+1} - V_r) needs one difference.  Lane r keeps
+// table; faces wholly above it add nothing.  So c A (V_{r+1} - V_r) needs the
+// sum of the voxels between the two planes' first voxels f and f' (one or two
+// at the scanned geometries: a detector row's height at the pixel is about a
+// voxel height), gathered from z-contiguous voxel columns.  Lane r keeps
 // c A (range sum) - G_r and G_r apart; the G of the plane above is added once
 // at the end through LDS.  The top detector edge (plane nv) has no lane: its
 // G is summed lane-parallel over the strip's pixels in a fixed order.
@@ -26,7 +28,7 @@
 // not depend on the order of the atomic adds, so results stay deterministic,
 // and the owner converts its sum once at the end.  The grid is a power of two
 // chosen per workgroup from a bound on the sum of |terms| (records x straddled
-// faces x their volume x 2 max|x|, max|x| per volume from the prefix pass), so
+// faces x their volume x 2 max|x|, max|x| per volume from the column pass), so
 // the sum stays below 2^62 and each term keeps about 40 more bits than FP32
 // carries.  FP64 plans keep FP64 sums and read their results back round by
 // round.
@@ -50,14 +52,13 @@ constexpr int kRounds = 32;
 template <typename T, int NBAT>
 __device__ __forceinline__ void fwd_flush(const DevGeom &G, const unsigned char *rbuf,
                                           const double *ptau, const T *ptf, const T *pinv,
-                                          const double *__restrict__ P, int B, int b0,
+                                          const T *__restrict__ X, int B, int b0,
                                           const unsigned *jobs, T *res, const JobRound *rounds,
                                           int &pending, int &nrounds, int lane, T (&acc1)[NBAT],
                                           T (&acc2)[NBAT])
 {
     wave_sync();
     const int nz = G.nz;
-    const size_t colstride = (size_t)(nz + 1);
     for (int s = lane; s < pending; s += 64) {
         const unsigned jb = jobs[s];
         const int e = (int)(jb & 63u), q = (int)((jb >> 6) & 2047u), j = (int)((jb >> 17) & 2047u);
@@ -66,10 +67,9 @@ __device__ __forceinline__ void fwd_flush(const DevGeom &G, const unsigned char 
         const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev);
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) {
-            const double *Pc = P + ((size_t)R.pix * B + b0 + b) * colstride;
-            const double Pj = Pc[j];
-            const T xj = j < nz ? T(Pc[j + 1] - Pj) : T(0);  // x_j and x_{j-1}, zero outside
-            const T xm = j >= 1 ? T(Pj - Pc[j - 1]) : T(0);
+            const T *Xc = X + ((size_t)R.pix * B + b0 + b) * nz;
+            const T xj = j < nz ? Xc[j] : T(0);  // x_j and x_{j-1}, zero outside
+            const T xm = j >= 1 ? Xc[j - 1] : T(0);
             res[s * NBAT + b] = K * (xj - xm);
         }
     }
@@ -101,13 +101,12 @@ __device__ __forceinline__ void fwd_flush(const DevGeom &G, const unsigned char 
 template <typename T, int NBAT>
 __device__ __forceinline__ void fwd_flush_fixed(const DevGeom &G, const unsigned char *rbuf,
                                                 const double *ptau, const T *ptf, const T *pinv,
-                                                const double *__restrict__ P, int B, int b0,
+                                                const T *__restrict__ X, int B, int b0,
                                                 const unsigned *jobs, unsigned long long *gacc,
                                                 int nthr, const int (&esh)[NBAT], int &pending, int lane)
 {
     wave_sync();
     const int nz = G.nz;
-    const size_t colstride = (size_t)(nz + 1);
     for (int s = lane; s < pending; s += 64) {
         const unsigned jb = jobs[s];
         const int e = (int)(jb & 63u), q = (int)((jb >> 6) & 2047u), j = (int)((jb >> 17) & 2047u);
@@ -116,10 +115,9 @@ __device__ __forceinline__ void fwd_flush_fixed(const DevGeom &G, const unsigned
         const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev);
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) {
-            const double *Pc = P + ((size_t)R.pix * B + b0 + b) * colstride;
-            const double Pj = Pc[j];
-            const T xj = j < nz ? T(Pc[j + 1] - Pj) : T(0);  // x_j and x_{j-1}, zero outside
-            const T xm = j >= 1 ? T(Pj - Pc[j - 1]) : T(0);
+            const T *Xc = X + ((size_t)R.pix * B + b0 + b) * nz;
+            const T xj = j < nz ? Xc[j] : T(0);  // x_j and x_{j-1}, zero outside
+            const T xm = j >= 1 ? Xc[j - 1] : T(0);
             const T v = K * (xj - xm);
             const long long fx = __double2ll_rn(ldexp((double)v, esh[b]));
             atomicAdd(&gacc[(size_t)b * nthr + q], (unsigned long long)fx);
@@ -130,12 +128,12 @@ __device__ __forceinline__ void fwd_flush_fixed(const DevGeom &G, const unsigned
 }
 
 // The single-volume FP32 instance is held to 64 VGPRs (8 waves per SIMD): the
-// extra waves hide the latency of the prefix-sum gathers better than the few
-// registers the limit spills cost; the other instances keep their registers.
+// extra waves hide the latency of the voxel gathers; the other instances keep
+// their registers.
 template <typename T, int NBAT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(NBAT == 1 && sizeof(T) == 4 ? 8 : 1)))
 fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
-             const int *__restrict__ soff, const double *__restrict__ P,
+             const int *__restrict__ soff, const T *__restrict__ X,
              const unsigned *__restrict__ xmax, T *__restrict__ y, int B, int b0, int qcap)
 {
     constexpr bool fixed = sizeof(T) == 4;  // fixed-point straddle sums (FP32 plans)
@@ -176,7 +174,6 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     const Rec<T> *Rs = recs + strip * RL.cap;
     const T inv_c = T(1.0 / G.c), z0c = T(G.z0 / G.c);
     const T cT = T(G.c);
-    const size_t colstride = (size_t)(nz + 1);
 
     // lane r: plane r is the lower edge of row r (lanes past nv carry tau = 0
     // and queue nothing)
@@ -232,10 +229,10 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             }
         }
         __syncthreads();
-        // software pipeline: the prefix-sum gathers of record e + 1 are issued
-        // before record e is used (indices of an empty record are clamped, so its
-        // loads stay in range and are not used)
-        auto faces = [&](int e, int &fa, int &je, int &f, int &f1, int &f2) {
+        // software pipeline: the voxel gathers of record e + 1 are issued before
+        // record e is used (indices are clamped into the column, so the loads of
+        // an empty record stay in range and are not used)
+        auto faces = [&](int e, int &fa, int &je, int &f, int &f1) {
             const Rec<T> &R = Rs[c0 + e];
             const int n = R.n > 0 ? R.n : 1;
             const double lc = R.lc;
@@ -251,40 +248,35 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             int fa1, fb1;
             face_split<T>(lo1, hi1, inv_c, z0c, nz, fa1, fb1);
             f1 = max(fa1 - 1, 0);
-            f2 = f + 1 < nz ? f + 1 : nz;
         };
-        int nfa = 0, nje = 0, nf = 0, nf1 = 0, nf2 = 0;
-        double np0[NBAT], np1[NBAT], npf[NBAT];
-        if (cnt > 0) {
-            faces(0, nfa, nje, nf, nf1, nf2);
-            const int pix = Rs[c0].pix;
+        // x_f and x_{f+1} of the next record (f <= nz, so f + 1 is clamped)
+        auto gather = [&](int e, int f, T (&xa)[NBAT], T (&xb)[NBAT]) {
+            const int pix = Rs[c0 + e].pix;
+            const int ia = f < nz ? f : nz - 1, ib = f + 1 < nz ? f + 1 : nz - 1;
 #pragma unroll
             for (int b = 0; b < NBAT; ++b) {
-                const double *Pn = P + ((size_t)pix * B + b0 + b) * colstride;
-                np0[b] = Pn[nf];
-                np1[b] = Pn[nf2];
-                npf[b] = Pn[nf1];
+                const T *Xn = X + ((size_t)pix * B + b0 + b) * nz;
+                xa[b] = Xn[ia];
+                xb[b] = Xn[ib];
             }
+        };
+        int nfa = 0, nje = 0, nf = 0, nf1 = 0;
+        T nxa[NBAT], nxb[NBAT];
+        if (cnt > 0) {
+            faces(0, nfa, nje, nf, nf1);
+            gather(0, nf, nxa, nxb);
         }
         for (int e = 0; e < cnt; ++e) {
-            const int fa = nfa, je = nje, f = nf;
-            double p0v[NBAT], p1v[NBAT], pfv[NBAT];
+            const int fa = nfa, je = nje, f = nf, f1 = nf1;
+            T xa[NBAT], xb[NBAT];
 #pragma unroll
             for (int b = 0; b < NBAT; ++b) {
-                p0v[b] = np0[b];
-                p1v[b] = np1[b];
-                pfv[b] = npf[b];
+                xa[b] = nxa[b];
+                xb[b] = nxb[b];
             }
             if (e + 1 < cnt) {
-                faces(e + 1, nfa, nje, nf, nf1, nf2);
-                const int pix = Rs[c0 + e + 1].pix;
-#pragma unroll
-                for (int b = 0; b < NBAT; ++b) {
-                    const double *Pn = P + ((size_t)pix * B + b0 + b) * colstride;
-                    np0[b] = Pn[nf];
-                    np1[b] = Pn[nf2];
-                    npf[b] = Pn[nf1];
-                }
+                faces(e + 1, nfa, nje, nf, nf1);
+                gather(e + 1, nf, nxa, nxb);
             }
             const Rec<T> &R = Rs[c0 + e];  // uniform fields through the scalar cache
             const int n = R.n;
@@ -294,11 +286,20 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             const double lbar = lc + (double)R.lbo;
             const T cA = cT * S.A;
             const T Klin = S.A * T(tau0 * lbar - (G.z0 + (double)f * G.c));
-            const bool lin = fa >= 1 && fa <= nz;
+            const bool lin = fa >= 1 && fa <= nz;  // then f = fa - 1 < nz
+            // voxels f .. f1 - 1 lie between the two planes' first voxels
+            T rs[NBAT];
+#pragma unroll
+            for (int b = 0; b < NBAT; ++b)
+                rs[b] = (f1 > f ? xa[b] : T(0)) + (f1 > f + 1 ? xb[b] : T(0));
+            for (int j = f + 2; j < f1; ++j) {  // taller spans: rare, loaded in place
+#pragma unroll
+                for (int b = 0; b < NBAT; ++b) rs[b] += X[((size_t)R.pix * B + b0 + b) * nz + j];
+            }
 #pragma unroll
             for (int b = 0; b < NBAT; ++b) {
-                const T gs = lin ? Klin * T(p1v[b] - p0v[b]) : T(0);
-                acc1[b] += cA * T(pfv[b] - p0v[b]) - gs;
+                const T gs = lin ? Klin * xa[b] : T(0);
+                acc1[b] += cA * rs[b] - gs;
                 acc2[b] += gs;
             }
             // queue the straddled faces fa .. je, one ballot round per face
@@ -309,10 +310,10 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
                 if (bal == 0ull) break;
                 if (fixed) {
                     if (pending > qcap - 64)
-                        fwd_flush_fixed<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, gacc, nthr,
+                        fwd_flush_fixed<T, NBAT>(G, rbuf, ptau, ptf, pinv, X, B, b0, jobs, gacc, nthr,
                                                  esh, pending, lane);
                 } else if (pending > qcap - 64 || nrounds == kRounds) {
-                    fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
+                    fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, X, B, b0, jobs, res, rounds, pending,
                                        nrounds, lane, acc1, acc2);
                 }
                 if (want) {
@@ -329,20 +330,20 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             }
             if (pending >= 64) {
                 if (fixed)
-                    fwd_flush_fixed<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, gacc, nthr, esh,
+                    fwd_flush_fixed<T, NBAT>(G, rbuf, ptau, ptf, pinv, X, B, b0, jobs, gacc, nthr, esh,
                                              pending, lane);
                 else
-                    fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
+                    fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, X, B, b0, jobs, res, rounds, pending,
                                        nrounds, lane, acc1, acc2);
             }
         }
         // jobs refer to this chunk's records: evaluate them before restaging
         if (pending > 0) {
             if (fixed)
-                fwd_flush_fixed<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, gacc, nthr, esh,
+                fwd_flush_fixed<T, NBAT>(G, rbuf, ptau, ptf, pinv, X, B, b0, jobs, gacc, nthr, esh,
                                          pending, lane);
             else
-                fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, P, B, b0, jobs, res, rounds, pending,
+                fwd_flush<T, NBAT>(G, rbuf, ptau, ptf, pinv, X, B, b0, jobs, res, rounds, pending,
                                    nrounds, lane, acc1, acc2);
         }
         // top detector edge: lane e takes record c0 + e (fields from LDS)
@@ -354,12 +355,12 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
                 const double lc = R.lc;
                 const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
                 const double lbar = lc + (double)R.lbo;
-                const double *Pc[NBAT];
+                const T *Xc[NBAT];
 #pragma unroll
-                for (int b = 0; b < NBAT; ++b) Pc[b] = P + ((size_t)R.pix * B + b0 + b) * colstride;
+                for (int b = 0; b < NBAT; ++b) Xc[b] = X + ((size_t)R.pix * B + b0 + b) * nz;
                 int f;
                 T gs[NBAT];
-                plane_G<T, NBAT>(G, S, lc, lbar, Llo, Lhi, tauT, tfT, invT, inv_c, z0c, Pc, f, gs);
+                plane_G<T, NBAT>(G, S, lc, lbar, Llo, Lhi, tauT, tfT, invT, inv_c, z0c, Xc, f, gs);
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) accT[b] += gs[b];
             }
@@ -432,20 +433,20 @@ static int fwd3d_qcap(const LaunchCfg &L)
 
 template <typename T, int NBAT>
 static hipError_t launch_fwd3d_t(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, int v0,
-                                 int nvc, const Rec<T> *recs, const int *soff, const double *P,
+                                 int nvc, const Rec<T> *recs, const int *soff, const T *X,
                                  const unsigned *xmax, T *y, int B, int b0, hipStream_t st)
 {
     const int qcap = fwd3d_qcap<T, NBAT>(L);
     if (qcap == 0) return hipErrorInvalidValue;
     const size_t lds = fwd3d_lds<T, NBAT>(L, qcap);
     hipLaunchKernelGGL((fwd3d_kernel<T, NBAT>), dim3(nvc * G.nu), dim3(L.fwd_threads), lds, st, G,
-                       RL, v0, recs, soff, P, xmax, y, B, b0, qcap);
+                       RL, v0, recs, soff, X, xmax, y, B, b0, qcap);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_fwd3d_all(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL,
-                                   int v0, int nvc, void *ws, const double *P, const unsigned *xmax,
+                                   int v0, int nvc, void *ws, const T *X, const unsigned *xmax,
                                    T *y, int B, hipStream_t st)
 {
     RecPtrs RP = rec_ptrs(RL, ws, sizeof(Rec<T>));
@@ -457,9 +458,9 @@ static hipError_t launch_fwd3d_all(const DevGeom &G, const LaunchCfg &L, const R
     // two launches of four at 256^3 (register pressure of the eight sums)
     for (int b0 = 0; b0 < B && e == hipSuccess;) {
         const int rem = B - b0;
-        if (rem >= 4 && fit4) { e = launch_fwd3d_t<T, 4>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 4; }
-        else if (rem >= 2 && fit2) { e = launch_fwd3d_t<T, 2>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 2; }
-        else { e = launch_fwd3d_t<T, 1>(G, L, RL, v0, nvc, recs, RP.soff, P, xmax, y, B, b0, st); b0 += 1; }
+        if (rem >= 4 && fit4) { e = launch_fwd3d_t<T, 4>(G, L, RL, v0, nvc, recs, RP.soff, X, xmax, y, B, b0, st); b0 += 4; }
+        else if (rem >= 2 && fit2) { e = launch_fwd3d_t<T, 2>(G, L, RL, v0, nvc, recs, RP.soff, X, xmax, y, B, b0, st); b0 += 2; }
+        else { e = launch_fwd3d_t<T, 1>(G, L, RL, v0, nvc, recs, RP.soff, X, xmax, y, B, b0, st); b0 += 1; }
     }
     return e;
 }
@@ -470,11 +471,11 @@ bool fwd3d_fits(const LaunchCfg &L, bool fp64)
 }
 
 hipError_t launch_fwd3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,
-                        int v0, int nvc, void *ws, const double *P, const unsigned *xmax, void *y,
+                        int v0, int nvc, void *ws, const void *X, const unsigned *xmax, void *y,
                         int B, hipStream_t st)
 {
-    if (fp64) return launch_fwd3d_all<double>(G, L, RL, v0, nvc, ws, P, nullptr, (double *)y, B, st);
-    return launch_fwd3d_all<float>(G, L, RL, v0, nvc, ws, P, xmax, (float *)y, B, st);
+    if (fp64) return launch_fwd3d_all<double>(G, L, RL, v0, nvc, ws, (const double *)X, nullptr, (double *)y, B, st);
+    return launch_fwd3d_all<float>(G, L, RL, v0, nvc, ws, (const float *)X, xmax, (float *)y, B, st);
 }
 
 }  // namespace smk

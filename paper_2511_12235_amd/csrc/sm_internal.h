@@ -73,16 +73,16 @@ hipError_t launch_records(const DevGeom &G, const RecLayout &RL, bool fp64, int 
                           void *ws, hipStream_t st);
 hipError_t launch_strip_count(const DevGeom &G, int *max_count, hipStream_t st);
 
-// x[B][nz][ny][nx] -> FP64 prefix sums along z, P[ny*nx][B][nz + 1]; for FP32
-// volumes also xmax[B] = bits of max |x| per batch element
-hipError_t launch_prefix_columns(const void *x, double *P, unsigned *xmax, bool fp64, int B, int nz,
-                                 int ny, int nx, hipStream_t st);
+// x[B][nz][ny][nx] -> voxel columns X[ny*nx][B][nz] (same element type); for
+// FP32 volumes also xmax[B] = bits of max |x| per batch element
+hipError_t launch_to_columns(const void *x, void *X, unsigned *xmax, bool fp64, int B, int nz, int ny,
+                            int nx, hipStream_t st);
 // sum over g of xt[g][ny*nx][B][nz] -> x[B][nz][ny][nx] (partials added in order)
 hipError_t launch_from_columns(const void *xt, void *x, int elem, int B, int nz, int ny, int nx,
                                int groups, hipStream_t st);
 
 hipError_t launch_fwd3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,
-                        int v0, int nvc, void *ws, const double *P, const unsigned *xmax, void *y,
+                        int v0, int nvc, void *ws, const void *X, const unsigned *xmax, void *y,
                         int B, hipStream_t st);
 hipError_t launch_back3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &RL, bool fp64,
                          int v0, int nvc, void *ws, const void *y, void *xt, int B, bool first,

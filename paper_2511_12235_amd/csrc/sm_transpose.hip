@@ -1,10 +1,10 @@
 // sm_transpose.hip -- layout changes between the caller's volume layout
 // x[B][nz][ny][nx] and the column layouts the cone-beam kernels use:
-//   forward input : FP64 prefix sums along z, P[ny*nx][B][nz + 1] with
-//                   P[.][.][0] = 0 and P[.][.][i+1] = x_0 + ... + x_i, so any
-//                   run of voxels of a column sums with one subtraction, and
-//                   (FP32) the largest |x| of every batch element, which sets
-//                   the fixed-point grid of the forward's straddle sums;
+//   forward input : voxel columns X[ny*nx][B][nz] (z contiguous, the plan's
+//                   precision), which the forward gathers a few voxels at a
+//                   time, and (FP32) the largest |x| of every batch element,
+//                   which sets the fixed-point grid of the forward's straddle
+//                   sums;
 //   adjoint output: xt[g][ny*nx][B][nz] (z contiguous), one partial volume per
 //                   view run g, summed in order and transposed back here.
 // Both go through LDS so global reads and writes stay coalesced.
@@ -18,17 +18,19 @@ __global__ void zero_u32_kernel(unsigned *p, int n)
     if (i < n) p[i] = 0u;
 }
 
-// One workgroup per (PW = 2^pwl consecutive pixels of one row, batch element).
-// xmax (FP32 only, else NULL): bits of max |x| per batch element, raised with
-// an integer max (non-negative floats order like their bit patterns).
+// One workgroup per (PW = 2^pwl consecutive pixels of one row, batch element):
+// the PW columns pass through LDS (row stride nz + 1, so that the transposing
+// writes hit distinct banks) and leave z-contiguous.  xmax (FP32 only, else
+// NULL): bits of max |x| per batch element, raised with an integer max
+// (non-negative floats order like their bit patterns).
 template <typename T>
-__global__ void __launch_bounds__(256) prefix_kernel(const T *__restrict__ x, double *__restrict__ P,
+__global__ void __launch_bounds__(256) columns_kernel(const T *__restrict__ x, T *__restrict__ X,
                                                       unsigned *__restrict__ xmax, int B, int nz,
                                                       int ny, int nx, int pwl)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned wmax[4];
-    double *col = reinterpret_cast<double *>(smem);  // [PW][nz + 1]
+    T *col = reinterpret_cast<T *>(smem);  // [PW][nz + 1]
     const int tid = threadIdx.x;
     const int PW = 1 << pwl;
     const int nxb = (nx + PW - 1) / PW;
@@ -38,13 +40,12 @@ __global__ void __launch_bounds__(256) prefix_kernel(const T *__restrict__ x, do
     const int iy = rem / nxb, ix0 = (rem - iy * nxb) * PW;
     const int w = min(PW, nx - ix0);
     const int cs = nz + 1;
-    // load: PW consecutive x values per z slice
     unsigned m = 0u;
-    for (int q = tid; q < PW * nz; q += blockDim.x) {
+    for (int q = tid; q < PW * nz; q += blockDim.x) {  // PW consecutive x values per z slice
         const int iz = q >> pwl, i = q & (PW - 1);
         if (i < w) {
             const T v = x[(((size_t)b * nz + iz) * ny + iy) * nx + ix0 + i];
-            col[i * cs + iz + 1] = (double)v;
+            col[i * cs + iz] = v;
             if (sizeof(T) == 4) m = max(m, __float_as_uint(fabsf((float)v)));
         }
     }
@@ -59,18 +60,9 @@ __global__ void __launch_bounds__(256) prefix_kernel(const T *__restrict__ x, do
         for (int i = 1; i < (int)(blockDim.x >> 6); ++i) mb = max(mb, wmax[i]);
         atomicMax(&xmax[b], mb);
     }
-    if (tid < w) {  // sequential scan per column (fixed order)
-        double run = 0.0;
-        col[tid * cs] = 0.0;
-        for (int iz = 1; iz <= nz; ++iz) {
-            run += col[tid * cs + iz];
-            col[tid * cs + iz] = run;
-        }
-    }
-    __syncthreads();
     for (int i = 0; i < w; ++i) {
-        double *dst = P + (((size_t)iy * nx + ix0 + i) * B + b) * cs;
-        for (int iz = tid; iz < cs; iz += blockDim.x) dst[iz] = col[i * cs + iz];
+        T *dst = X + (((size_t)iy * nx + ix0 + i) * B + b) * nz;
+        for (int iz = tid; iz < nz; iz += blockDim.x) dst[iz] = col[i * cs + iz];
     }
 }
 
@@ -100,22 +92,23 @@ __global__ void __launch_bounds__(256) from_columns_kernel(const T *__restrict__
     }
 }
 
-hipError_t launch_prefix_columns(const void *x, double *P, unsigned *xmax, bool fp64, int B, int nz,
-                                 int ny, int nx, hipStream_t st)
+hipError_t launch_to_columns(const void *x, void *X, unsigned *xmax, bool fp64, int B, int nz, int ny,
+                            int nx, hipStream_t st)
 {
+    const size_t es = fp64 ? 8 : 4;
     int pwl = 4;  // 16 pixels per workgroup while the columns fit in 48 KiB of LDS
-    while (pwl > 0 && sizeof(double) * ((size_t)1 << pwl) * (size_t)(nz + 1) > 49152) --pwl;
+    while (pwl > 0 && es * ((size_t)1 << pwl) * (size_t)(nz + 1) > 49152) --pwl;
     const int PW = 1 << pwl;
     const int nxb = (nx + PW - 1) / PW;
     const dim3 grid((unsigned)B * ny * nxb);
-    const size_t lds = sizeof(double) * PW * (size_t)(nz + 1);
+    const size_t lds = es * PW * (size_t)(nz + 1);
     if (fp64) {
-        hipLaunchKernelGGL(prefix_kernel<double>, grid, dim3(256), lds, st, (const double *)x, P,
-                           (unsigned *)nullptr, B, nz, ny, nx, pwl);
+        hipLaunchKernelGGL(columns_kernel<double>, grid, dim3(256), lds, st, (const double *)x,
+                           (double *)X, (unsigned *)nullptr, B, nz, ny, nx, pwl);
     } else {
         hipLaunchKernelGGL(zero_u32_kernel, dim3((B + 255) / 256), dim3(256), 0, st, xmax, B);
-        hipLaunchKernelGGL(prefix_kernel<float>, grid, dim3(256), lds, st, (const float *)x, P, xmax,
-                           B, nz, ny, nx, pwl);
+        hipLaunchKernelGGL(columns_kernel<float>, grid, dim3(256), lds, st, (const float *)x, (float *)X,
+                           xmax, B, nz, ny, nx, pwl);
     }
     return hipGetLastError();
 }

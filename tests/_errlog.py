@@ -52,9 +52,9 @@ def digest(log, out, command):
              "command: %s" % command,
              "err: relative L2 (kind rel_l2), or the normalised mismatch the case states (kind)",
              "max_rel: max |got - ref| / max(|ref|, 1e-3 max|ref|) over the compared elements",
-             "", "%-60s %-10s %10s %10s %10s %8s" % ("case", "kind", "err", "max_rel", "n", "bar")]
+             "", "%-72s %-11s %10s %10s %10s %8s" % ("case", "kind", "err", "max_rel", "n", "bar")]
     for r in rows:
-        lines.append("%-60s %-10s %10.3e %10.3e %10d %8.0e" % (r["case"][:60], r["kind"], r["err"],
+        lines.append("%-72s %-11s %10.3e %10.3e %10d %8.0e" % (r["case"][:72], r["kind"], r["err"],
                                                              r["max_rel"], r["n"], r["bar"]))
     worst = {}
     for r in rows:

@@ -102,6 +102,6 @@ def test_plane_through_face(name, nudge, prec):
     row = W.T @ f
     rg = A.back(_t(f.reshape(g.sino_shape), prec)).double().cpu().numpy().ravel()
     err_r = float(np.abs(rg - row).max()) / vol
-    note("near tie, max |error| / voxel volume, " + tag, max(err_c, err_r), max(err_c, err_r), 2, TOL[prec],
-         kind="max_abs_vol")
+    note("near tie %s, max|err|/voxel, %s nudge %+d" % (prec, name, nudge), max(err_c, err_r),
+         max(err_c, err_r), 2, TOL[prec], kind="max_abs_vol")
     assert err_c <= TOL[prec] and err_r <= TOL[prec], (err_c, err_r)
