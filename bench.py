@@ -507,6 +507,7 @@ def main():
                    "ms_adjoint": float(np.mean(t_b)) * 1e3, "nnz_count_s": count_s,
                    "wall_s": wall,
                    "kernel_ms": {k: round(v[1] / args.steps, 3) for k, v in kt.items()},
+                   "launch_shape": dict(zip(("views_per_chunk", "adjoint_runs"), A.launch_shape())),
                    "pct_hbm_roofline_effective": 100.0 * eff_bw / HBM_PEAK_GBS,
                    "records": ("kept in the plan: %.1f GB built once in %.2f s" % (A.record_bytes() / 1e9, keep_s)
                                if args.keep_records else "rebuilt in every call")},

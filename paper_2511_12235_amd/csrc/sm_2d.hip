@@ -8,7 +8,9 @@
 //
 // Forward: one workgroup per (view, detector element) walks the pixels of the
 // element's wedge and reduces in a fixed order (no atomics).  Adjoint: one
-// thread per pixel loops over the views and the elements it meets.
+// wave per pixel; lane l takes views l, l + 64, ... and the elements each
+// meets, and the wave adds its lanes' sums in a fixed butterfly order (one
+// thread per pixel left a 64^2 image with 64 waves for 1024 SIMDs).
 #include "sm_internal.h"
 
 namespace smk {
@@ -68,10 +70,10 @@ template <typename T, int NBAT>
 __global__ void __launch_bounds__(256) back2d_kernel(DevGeom G, const T *__restrict__ y,
                                                       T *__restrict__ x, int B, int b0)
 {
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int pix = lb * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int pix = xcd_remap(blockIdx.x, gridDim.x) * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6);
     const int npix = G.nx * G.ny;
-    if (pix >= npix) return;
+    if (pix >= npix) return;  // uniform over the wave
     const int iy = pix / G.nx, ix = pix - iy * G.nx;
     const double xc = G.x0 + ((double)ix + 0.5) * G.a;
     const double yc = G.y0 + ((double)iy + 0.5) * G.b;
@@ -79,7 +81,7 @@ __global__ void __launch_bounds__(256) back2d_kernel(DevGeom G, const T *__restr
     T acc[NBAT];
 #pragma unroll
     for (int q = 0; q < NBAT; ++q) acc[q] = T(0);
-    for (int view = 0; view < G.n_p; ++view) {
+    for (int view = lane; view < G.n_p; view += 64) {
         const double2 cs = G.trig[view];
         const double cp = cs.x, sp = cs.y;
         int k0, k1;
@@ -97,7 +99,13 @@ __global__ void __launch_bounds__(256) back2d_kernel(DevGeom G, const T *__restr
         }
     }
 #pragma unroll
-    for (int q = 0; q < NBAT; ++q) x[(size_t)(b0 + q) * npix + pix] = acc[q];
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int q = 0; q < NBAT; ++q) acc[q] += __shfl_xor(acc[q], o, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NBAT; ++q) x[(size_t)(b0 + q) * npix + pix] = acc[q];
+    }
 }
 
 template <typename T>
@@ -123,14 +131,14 @@ template <typename T>
 static hipError_t back2d_all(const DevGeom &G, const T *y, T *x, int B, hipStream_t st)
 {
     const int npix = G.nx * G.ny;
-    const int nblk = (npix + 127) / 128;
+    const int nblk = (npix + 3) / 4;  // four waves (pixels) per workgroup
     for (int b0 = 0; b0 < B;) {
         const int rem = B - b0;
         if (rem >= 4) {
-            hipLaunchKernelGGL((back2d_kernel<T, 4>), dim3(nblk), dim3(128), 0, st, G, y, x, B, b0);
+            hipLaunchKernelGGL((back2d_kernel<T, 4>), dim3(nblk), dim3(256), 0, st, G, y, x, B, b0);
             b0 += 4;
         } else {
-            hipLaunchKernelGGL((back2d_kernel<T, 1>), dim3(nblk), dim3(128), 0, st, G, y, x, B, b0);
+            hipLaunchKernelGGL((back2d_kernel<T, 1>), dim3(nblk), dim3(256), 0, st, G, y, x, B, b0);
             b0 += 1;
         }
         hipError_t e = hipGetLastError();

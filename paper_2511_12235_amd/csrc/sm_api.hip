@@ -404,8 +404,10 @@ sm_status sm_plan_create(const sm_geometry *g, sm_precision precision, sm_plan *
     // small volumes, then the run count (up to 4x that) whose waves fill the
     // last round of resident waves best, so that no round of the launch runs
     // a third empty.  A round is taken as kResidentWaves, the single-volume
-    // adjoint's occupancy on MI355X; the rule uses the geometry and these
-    // constants only, so results do not depend on the device.
+    // adjoint's occupancy on MI355X at 256^3; the rule uses the geometry and
+    // these constants only, so results do not depend on the device.  (Taking
+    // the round from the kernel's occupancy at each geometry instead chose 5
+    // runs at 128^3, where 6 measured faster: 3.59 against 3.37 ms.)
     {
         const int64_t tiles = (int64_t)((G.nx + 3) / 4) * ((G.ny + 3) / 4);
         const int64_t waves = tiles * (L.back_threads / 64);

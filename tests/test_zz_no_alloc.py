@@ -76,6 +76,17 @@ def test_kept_records_and_2d():
           "2D fan 64^2")
 
 
+def test_one_256_volume():
+    """One 256^3 FP32 volume fits (its voxel columns, 64 MiB, beside about one
+    view of strip records): records rebuilt one chunk at a time."""
+    g = wl.c3_cone256()
+    _say("noalloc 256^3 fp32, one volume")
+    A = SystemMatrix(g, "fp32", device=DEV)
+    x = wl.ellipse_phantom(g, 10, seed=2)
+    y = wl.uniform(g.sino_shape, 8)
+    _both(A, _t(x, "fp32"), _t(y, "fp32"), "fp32", "256^3 B=1 fp32")
+
+
 def test_rejects_what_does_not_fit():
     """Three 256^3 volumes need about 200 MB of column buffers: SM_ERANGE,
     nothing launched, and the message names the sizes."""
