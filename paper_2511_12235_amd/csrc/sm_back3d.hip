@@ -123,8 +123,13 @@ __device__ __forceinline__ bool tile_columns(const DevGeom &G, const int2 *__res
     return true;
 }
 
+// The single-volume FP32 instance is held to 80 VGPRs (6 waves per SIMD,
+// which its LDS allows at 256^3); left to the 1024-thread bound the compiler
+// takes 81 and the kernel runs at 5.  The other instances measured slower
+// under the same hint (spills, or a different schedule).
 template <typename T, int NBAT, int TX, int TY>
 __global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NBAT == 1 ? 6 : 1)))
 back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict__ recs,
               const int *__restrict__ sj0, const int *__restrict__ soff,
               const int2 *__restrict__ pixk, const T *__restrict__ y, T *__restrict__ xt, int B,
@@ -213,7 +218,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
                 const Rec<T> &R = rtab[p * rspan + (k - k0)];  // LDS copy
                 const int n = __builtin_amdgcn_readfirstlane(R.n);
                 if (n == 0) continue;
-                const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
+                const StripTab<T> S = strip_tab<T>(R.tab, R.tab, R.M1);
                 const T *Y = patch + (size_t)(k - kmin) * rowstride + 1;  // Y[-1] .. Y[nv]
                 T sum[NBAT];
                 adj_terms<T, NBAT>(S, R.lc, R.lbo, R.kLo, R.kHi, ptau, dtau, ptf, pinv, za, zb, v0dv,

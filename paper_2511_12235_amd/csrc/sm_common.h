@@ -57,15 +57,16 @@ constexpr int MAXV = 6;  // vertices of a strip polygon (rectangle cut by two li
 // tab[i] = (depth l', chord width w, S0, S1) for the breakpoints in ascending
 // depth, S0 = integral of w beyond the depth, S1 = first moment of w beyond
 // the depth about the depth itself.  Area = tab[0][2].  The header also holds
-// the area-weighted mean depth relative to lc and the row-plane index scales
+// the first moment of the chord width about the pixel centre, the
+// area-weighted mean depth relative to lc and the row-plane index scales
 // D / (L dv) at the nearest and farthest depth L (see plane_split), all
 // computed in FP64.  128 bytes for T = float, 240 for T = double.
 template <typename T>
 struct alignas(16) Rec {
     double lc;  // depth of the pixel centre
     int n;      // number of breakpoints, 0 when the polygon is empty
-    int k;      // detector column
     int pix;    // pixel index iy * nx + ix
+    T M1;       // S1 + d0 A: integral of l' w(l') dl' over the strip
     T lbo;      // area-weighted mean depth minus lc
     T kLo, kHi; // D / (Llo dv), D / (Lhi dv)
     T tab[MAXV][4];
@@ -188,7 +189,7 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
     }
 
     R.lc = lc;
-    R.k = k;
+    R.M1 = T(0);
     R.lbo = T(0);
     R.kLo = T(0);
     R.kHi = T(0);
@@ -269,6 +270,7 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
     R.n = S0[0] > 0.0 ? m : 0;
     if (S0[0] > 0.0) {
         const double Ddv = G.D / G.dv;
+        R.M1 = T(S1[0] + bd[0] * S0[0]);
         R.lbo = T(bd[0] + qdiv_(S1[0], S0[0]));
         R.kLo = T(qdiv_(Ddv, lc + bd[0]));
         R.kHi = T(qdiv_(Ddv, lc + dlast));
@@ -411,19 +413,18 @@ __host__ __device__ inline void face_split(T lo, T hi, T inv_c, T z0c, int nz, i
 template <typename T>
 struct StripTab {
     const T (*tab)[4];
-    T d0, A, S1, M1, b1, b2, b3, b4;  // nearest depth, area, first moments about d0 and the
-                                      // column centre, interior breakpoints
+    T d0, A, M1, b1, b2, b3, b4;  // nearest depth, area, first moment about the column
+                                  // centre, interior breakpoints
 };
 
 template <typename T>
-__host__ __device__ inline StripTab<T> strip_tab(const T (*tab)[4], const T (*rows)[4])
+__host__ __device__ inline StripTab<T> strip_tab(const T (*tab)[4], const T (*rows)[4], T M1)
 {
     StripTab<T> S;
     S.tab = rows;
     S.d0 = tab[0][0];
     S.A = tab[0][2];
-    S.S1 = tab[0][3];
-    S.M1 = S.S1 + S.d0 * S.A;
+    S.M1 = M1;
     S.b1 = tab[1][0];
     S.b2 = tab[2][0];
     S.b3 = tab[3][0];
@@ -545,12 +546,14 @@ __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, 
 //
 // The linear volumes are K_q = A (tau_q lbar - za) = A (alpha + (q - a) beta)
 // for q = a .. e - 1 (a = paa, e = pab), with A alpha = K_a and beta = dtau
-// lbar.  FP64 plans sum them by parts,
+// lbar.  Summed by parts,
 //     sum_q K_q (y[q-1] - y[q]) = A alpha (y[a-1] - y[e-1])
 //                                 + A beta sum_{q=a}^{e-2} (y[q] - y[e-1]),
-// so that their loop only adds row differences (one FP64 product per record
-// instead of one per plane); FP32 plans evaluate K_q per plane, which
-// measured faster in FP32 (40.9 against 43.7 ms per call at 256^3).
+// one FP64 product per record instead of one per plane.  A voxel holds one or
+// two planes (the row pitch is close to the voxel's projected height), so the
+// second sum is taken without a loop for e - a <= 2 and the loop runs only
+// for the rare e - a > 2.  Every batch width takes the same steps, so that a
+// volume's result does not depend on the batch it is applied in.
 template <typename T, int NBAT>
 __host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T lbo, T kLo, T kHi,
                                         const double *ptau, double dtau, double za, double zb, T v0dv,
@@ -561,25 +564,18 @@ __host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T lbo, 
     plane_split<T>(T(za), kLo, kHi, v0dv, nv, pha, paa);
     plane_split<T>(T(zb), kLo, kHi, v0dv, nv, phb, pab);
     const T cA = cT * S.A;
+    const int n = pab - paa;      // >= 0: zb > za
+    const int qa = min(paa, nv);  // a plane index even when n = 0 and a = nv + 1
+    T alpha = S.A * T(ptau[qa] * lbar - za);
+    alpha = n > 0 ? alpha : T(0);
+    const T beta = S.A * T(dtau * lbar);
 #pragma unroll
-    for (int b = 0; b < NBAT; ++b) sum[b] = cA * Y[b * ystride + pab - 1];
-    if constexpr (sizeof(T) == 4) {
-        for (int q = paa; q < pab; ++q) {
-            const T K = S.A * T(ptau[q] * lbar - za);
-#pragma unroll
-            for (int b = 0; b < NBAT; ++b) sum[b] += K * (Y[b * ystride + q - 1] - Y[b * ystride + q]);
-        }
-    } else if (pab > paa) {
-        const T alpha = S.A * T(ptau[paa] * lbar - za);
-        const T beta = S.A * T(dtau * lbar);
-#pragma unroll
-        for (int b = 0; b < NBAT; ++b) {
-            const T *Yb = Y + b * ystride;
-            const T ye = Yb[pab - 1];
-            T d = T(0);
-            for (int q = paa; q < pab - 1; ++q) d += Yb[q] - ye;
-            sum[b] += alpha * (Yb[paa - 1] - ye) + beta * d;
-        }
+    for (int b = 0; b < NBAT; ++b) {
+        const T *Yb = Y + b * ystride;
+        const T ye = Yb[pab - 1];
+        T d = n >= 2 ? Yb[qa] - ye : T(0);
+        for (int q = paa + 1; q < pab - 1; ++q) d += Yb[q] - ye;
+        sum[b] = fma(cA, ye, fma(alpha, Yb[qa - 1] - ye, beta * d));
     }
 }
 

@@ -68,7 +68,7 @@ __device__ __forceinline__ void fwd_flush(const DevGeom &G, const unsigned char 
         const int e = (int)(jb & 63u), q = (int)((jb >> 6) & 2047u), j = (int)((jb >> 17) & 2047u);
         const Rec<T> &R = lds_rec<T>(rbuf, e);
         const T ev = T(ptau[q] * R.lc - (G.z0 + (double)j * G.c));
-        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev);
+        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab, R.M1), ptf[q], pinv[q], ev);
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) {
             const T *Xc = X + ((size_t)R.pix * B + b0 + b) * nz;
@@ -116,7 +116,7 @@ __device__ __forceinline__ void fwd_flush_fixed(const DevGeom &G, const unsigned
         const int e = (int)(jb & 63u), q = (int)((jb >> 6) & 2047u), j = (int)((jb >> 17) & 2047u);
         const Rec<T> &R = lds_rec<T>(rbuf, e);
         const T ev = T(ptau[q] * R.lc - (G.z0 + (double)j * G.c));
-        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev);
+        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab, R.M1), ptf[q], pinv[q], ev);
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) {
             const T *Xc = X + ((size_t)R.pix * B + b0 + b) * nz;
@@ -286,7 +286,7 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             const Rec<T> &R = Rs[c0 + e];  // uniform fields through the scalar cache
             const int n = R.n;
             if (n == 0) continue;
-            const StripTab<T> S = strip_tab<T>(R.tab, lds_rec<T>(rbuf, e).tab);
+            const StripTab<T> S = strip_tab<T>(R.tab, lds_rec<T>(rbuf, e).tab, R.M1);
             const double lc = R.lc;
             const double lbar = lc + (double)R.lbo;
             const T cA = cT * S.A;
@@ -356,7 +356,7 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             const Rec<T> &R = lds_rec<T>(rbuf, tid);
             const int n = R.n;
             if (n > 0) {
-                const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
+                const StripTab<T> S = strip_tab<T>(R.tab, R.tab, R.M1);
                 const double lc = R.lc;
                 const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
                 const double lbar = lc + (double)R.lbo;
