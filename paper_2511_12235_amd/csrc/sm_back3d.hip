@@ -15,9 +15,10 @@
 // wholly below the voxel add nothing; planes wholly above it add c A each,
 // which telescopes to c A y[first such plane - 1].  Of the planes reaching
 // into the voxel, those wholly above za contribute the linear volume
-// A (tau lbar - za) at za; only planes straddling a face need the chord
-// table.  Chunks of views add into the z-contiguous workspace in a fixed
-// order, which is transposed to the caller's layout afterwards.
+// A (tau lc - za) at za (lc the strip's centroid depth); only planes
+// straddling a face need the chord table.  Chunks of views add into the
+// z-contiguous workspace in a fixed order, which is transposed to the
+// caller's layout afterwards.
 
 #include "sm_internal.h"
 
@@ -123,13 +124,8 @@ __device__ __forceinline__ bool tile_columns(const DevGeom &G, const int2 *__res
     return true;
 }
 
-// The single-volume FP32 instance is held to 80 VGPRs (6 waves per SIMD,
-// which its LDS allows at 256^3); left to the 1024-thread bound the compiler
-// takes 81 and the kernel runs at 5.  The other instances measured slower
-// under the same hint (spills, or a different schedule).
 template <typename T, int NBAT, int TX, int TY>
 __global__ void __launch_bounds__(1024)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NBAT == 1 ? 6 : 1)))
 back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict__ recs,
               const int *__restrict__ sj0, const int *__restrict__ soff,
               const int2 *__restrict__ pixk, const T *__restrict__ y, T *__restrict__ xt, int B,
@@ -175,9 +171,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
     const bool active = iz < nz;
     const double za = G.z0 + (double)iz * G.c;
     const double zb = G.z0 + (double)(iz + 1) * G.c;
-    const T cT = T(G.c);
     const T v0dv = T(G.v0 / G.dv);
-    const double dtau = G.dv / G.D;  // spacing of the plane slopes
 
     T acc[TP][NBAT];
 #pragma unroll
@@ -218,11 +212,11 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
                 const Rec<T> &R = rtab[p * rspan + (k - k0)];  // LDS copy
                 const int n = __builtin_amdgcn_readfirstlane(R.n);
                 if (n == 0) continue;
-                const StripTab<T> S = strip_tab<T>(R.tab, R.tab, R.M1);
+                const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
                 const T *Y = patch + (size_t)(k - kmin) * rowstride + 1;  // Y[-1] .. Y[nv]
                 T sum[NBAT];
-                adj_terms<T, NBAT>(S, R.lc, R.lbo, R.kLo, R.kHi, ptau, dtau, ptf, pinv, za, zb, v0dv,
-                                   nv, cT, Y, (size_t)pcols * rowstride, sum);
+                adj_terms<T, NBAT>(S, R.lc, R.cA, R.bA, R.kLo, R.kHi, ptau, ptf, pinv, za, zb, v0dv,
+                                   nv, Y, (size_t)pcols * rowstride, sum);
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) cur[b] += sum[b];
             }

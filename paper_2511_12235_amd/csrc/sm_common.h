@@ -53,22 +53,24 @@ struct DevGeom {
 
 constexpr int MAXV = 6;  // vertices of a strip polygon (rectangle cut by two lines)
 
-// Strip record: pixel `pix` cut by detector column k in one view.
-// tab[i] = (depth l', chord width w, S0, S1) for the breakpoints in ascending
-// depth, S0 = integral of w beyond the depth, S1 = first moment of w beyond
-// the depth about the depth itself.  Area = tab[0][2].  The header also holds
-// the first moment of the chord width about the pixel centre, the
-// area-weighted mean depth relative to lc and the row-plane index scales
-// D / (L dv) at the nearest and farthest depth L (see plane_split), all
-// computed in FP64.  128 bytes for T = float, 240 for T = double.
+// Strip record: pixel `pix` cut by detector column k in one view.  Depths
+// l' are measured from lc, the depth of the strip polygon's centroid (its
+// area-weighted mean depth), so that the first moment of the chord width
+// about the origin vanishes.  tab[i] = (depth l', chord width w, S0, S1) for
+// the breakpoints in ascending depth, S0 = integral of w beyond the depth,
+// S1 = first moment of w beyond the depth about the depth itself.  Area A =
+// tab[0][2].  The header also holds the row-plane index scales D / (L dv) at
+// the nearest and farthest depth L (see plane_split), c A and A lc dv / D
+// (the step of the linear volume A (tau lc - z) from one row plane to the
+// next), all computed in FP64.  128 bytes for T = float, 240 for T = double.
 template <typename T>
 struct alignas(16) Rec {
-    double lc;  // depth of the pixel centre
+    double lc;  // depth of the centroid
     int n;      // number of breakpoints, 0 when the polygon is empty
     int pix;    // pixel index iy * nx + ix
-    T M1;       // S1 + d0 A: integral of l' w(l') dl' over the strip
-    T lbo;      // area-weighted mean depth minus lc
     T kLo, kHi; // D / (Llo dv), D / (Lhi dv)
+    T cA;       // c A
+    T bA;       // A lc dv / D
     T tab[MAXV][4];
 };
 
@@ -189,10 +191,10 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
     }
 
     R.lc = lc;
-    R.M1 = T(0);
-    R.lbo = T(0);
     R.kLo = T(0);
     R.kHi = T(0);
+    R.cA = T(0);
+    R.bA = T(0);
     if (m < 3) {
         R.n = 0;
         return;
@@ -268,16 +270,19 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
         }
     }
     R.n = S0[0] > 0.0 ? m : 0;
+    double lbo = 0.0;  // centroid depth relative to the pixel centre
     if (S0[0] > 0.0) {
         const double Ddv = G.D / G.dv;
-        R.M1 = T(S1[0] + bd[0] * S0[0]);
-        R.lbo = T(bd[0] + qdiv_(S1[0], S0[0]));
+        lbo = bd[0] + qdiv_(S1[0], S0[0]);
+        R.lc = lc + lbo;
         R.kLo = T(qdiv_(Ddv, lc + bd[0]));
         R.kHi = T(qdiv_(Ddv, lc + dlast));
+        R.cA = T(G.c * S0[0]);
+        R.bA = T(S0[0] * qdiv_(G.dv, G.D) * R.lc);
     }
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
-        R.tab[i][0] = T(i < m ? bd[i] : dlast);
+        R.tab[i][0] = T((i < m ? bd[i] : dlast) - lbo);
         R.tab[i][1] = T(bw[i]);
         R.tab[i][2] = T(S0[i]);
         R.tab[i][3] = T(S1[i]);
@@ -358,7 +363,7 @@ __host__ __device__ inline T eval_K(const T (*tab)[4], int n, T tau, T inv_tau, 
 // lo = tau Llo, hi = tau Lhi for tau >= 0 (swapped for tau < 0), Llo / Lhi
 // being the nearest / farthest depth of the strip polygon.  Against a face at
 // height z a plane is wholly below (K = 0), wholly above (K = the linear
-// integral A (tau lbar - z), lbar the area-weighted mean depth) or straddles
+// integral A (tau lc - z), lc the centroid depth of the strip) or straddles
 // it (K from the chord table).  Both walks below only need the split to be
 // consistent: K_cut is exact for a sloped plane anywhere, and a plane put on
 // the wrong side of a face by rounding is off by a volume of rounding size.
@@ -413,18 +418,16 @@ __host__ __device__ inline void face_split(T lo, T hi, T inv_c, T z0c, int nz, i
 template <typename T>
 struct StripTab {
     const T (*tab)[4];
-    T d0, A, M1, b1, b2, b3, b4;  // nearest depth, area, first moment about the column
-                                  // centre, interior breakpoints
+    T d0, A, b1, b2, b3, b4;  // nearest depth, area, interior breakpoints
 };
 
 template <typename T>
-__host__ __device__ inline StripTab<T> strip_tab(const T (*tab)[4], const T (*rows)[4], T M1)
+__host__ __device__ inline StripTab<T> strip_tab(const T (*tab)[4], const T (*rows)[4])
 {
     StripTab<T> S;
     S.tab = rows;
     S.d0 = tab[0][0];
     S.A = tab[0][2];
-    S.M1 = M1;
     S.b1 = tab[1][0];
     S.b2 = tab[2][0];
     S.b3 = tab[3][0];
@@ -438,9 +441,10 @@ __host__ __device__ inline StripTab<T> strip_tab(const T (*tab)[4], const T (*ro
 // (Psi(lam) = S1 + (d0 - lam) A there) and is zero beyond the farthest, so
 // the result is exact wherever the plane lies.  For tau > 0, K = tau Psi(lam).
 // For tau < 0, writing (w)_+ = w + (-w)_+ gives the plane's linear volume
-// e A + tau M1 (M1 = S1 + d0 A, the first moment about the column centre)
-// plus (-tau) Psi(lam), so both signs take |tau| Psi and one select.  A
-// horizontal plane gets 0 (it never straddles a face; see above).
+// e A + tau M1 plus (-tau) Psi(lam), M1 being the first moment of the chord
+// width about the depth origin, which is zero at the centroid: both signs
+// take |tau| Psi and the negative one adds e A.  A horizontal plane gets 0
+// (it never straddles a face; see above).
 template <typename T>
 __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
 {
@@ -462,7 +466,7 @@ __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
     const T below = S.d0 - lam;
     psi += (below > T(0) ? below : T(0)) * S.A;
     const T kp = fabs(tau) * psi;
-    return tau < T(0) ? kp + (e * S.A + tau * S.M1) : kp;
+    return tau < T(0) ? kp + e * S.A : kp;
 }
 
 // Heights of plane tau over the strip [Llo, Lhi] (depths).
@@ -480,7 +484,7 @@ __host__ __device__ inline void plane_extent(T tau, T Llo, T Lhi, T &lo, T &hi)
 // terms come from straddle_term.  Xc[b] is the voxel column (x_0 .. x_{nz-1})
 // of batch element b.
 template <typename T, int NBAT>
-__host__ __device__ inline void plane_lin(const DevGeom &G, const StripTab<T> &S, double lbar,
+__host__ __device__ inline void plane_lin(const DevGeom &G, const StripTab<T> &S, double lc,
                                           T Llo, T Lhi, double tau, T tauf, T inv_c, T z0c,
                                           const T *const (&Xc)[NBAT], int &f_out, int &fa_out,
                                           int &je_out, T (&gs)[NBAT])
@@ -497,7 +501,7 @@ __host__ __device__ inline void plane_lin(const DevGeom &G, const StripTab<T> &S
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) gs[b] = T(0);
     if (fa >= 1 && fa <= nz) {  // face f wholly below the plane: linear volume
-        const T K = S.A * T(tau * lbar - (G.z0 + (double)f * G.c));
+        const T K = S.A * T(tau * lc - (G.z0 + (double)f * G.c));
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) gs[b] = K * Xc[b][f];  // f = fa - 1 < nz
     }
@@ -522,12 +526,11 @@ __host__ __device__ inline void straddle_term(const DevGeom &G, const StripTab<T
 // G_p of one plane for one strip record; f_out = first voxel not wholly below.
 template <typename T, int NBAT>
 __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, double lc,
-                                        double lbar, T Llo, T Lhi, double tau, T tauf, T invt,
-                                        T inv_c, T z0c, const T *const (&Xc)[NBAT], int &f_out,
-                                        T (&gs)[NBAT])
+                                        T Llo, T Lhi, double tau, T tauf, T invt, T inv_c, T z0c,
+                                        const T *const (&Xc)[NBAT], int &f_out, T (&gs)[NBAT])
 {
     int fa, je;
-    plane_lin<T, NBAT>(G, S, lbar, Llo, Lhi, tau, tauf, inv_c, z0c, Xc, f_out, fa, je, gs);
+    plane_lin<T, NBAT>(G, S, lc, Llo, Lhi, tau, tauf, inv_c, z0c, Xc, f_out, fa, je, gs);
     for (int j = fa; j <= je; ++j) {
         T t[NBAT];
         straddle_term<T, NBAT>(G, S, lc, tau, tauf, invt, j, Xc, t);
@@ -542,40 +545,38 @@ __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, 
 // above za that reach below zb.  Planes pha .. paa - 1 straddle za and
 // phb .. pab - 1 straddle zb (adj_straddle gives their terms).
 // Y[b * ystride + q] holds y[q] of batch element b for q in [-1, nv];
-// ptau holds the plane slopes in FP64, dtau = dv / D their spacing.
+// ptau holds the plane slopes in FP64; cA = c A and bA = A lc dv / D come
+// with the record.
 //
-// The linear volumes are K_q = A (tau_q lbar - za) = A (alpha + (q - a) beta)
-// for q = a .. e - 1 (a = paa, e = pab), with A alpha = K_a and beta = dtau
-// lbar.  Summed by parts,
-//     sum_q K_q (y[q-1] - y[q]) = A alpha (y[a-1] - y[e-1])
-//                                 + A beta sum_{q=a}^{e-2} (y[q] - y[e-1]),
+// The linear volumes are K_q = A (tau_q lc - za) = alpha + (q - a) bA for
+// q = a .. e - 1 (a = paa, e = pab; the slopes tau_q are dv / D apart), with
+// alpha = K_a.  Summed by parts,
+//     sum_q K_q (y[q-1] - y[q]) = alpha (y[a-1] - y[e-1])
+//                                 + bA sum_{q=a}^{e-2} (y[q] - y[e-1]),
 // one FP64 product per record instead of one per plane.  A voxel holds one or
 // two planes (the row pitch is close to the voxel's projected height), so the
 // second sum is taken without a loop for e - a <= 2 and the loop runs only
 // for the rare e - a > 2.  Every batch width takes the same steps, so that a
 // volume's result does not depend on the batch it is applied in.
 template <typename T, int NBAT>
-__host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T lbo, T kLo, T kHi,
-                                        const double *ptau, double dtau, double za, double zb, T v0dv,
-                                        int nv, T cT, const T *Y, size_t ystride, int &pha, int &paa,
-                                        int &phb, int &pab, T (&sum)[NBAT])
+__host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T cA, T bA, T kLo, T kHi,
+                                        const double *ptau, double za, double zb, T v0dv, int nv,
+                                        const T *Y, size_t ystride, int &pha, int &paa, int &phb,
+                                        int &pab, T (&sum)[NBAT])
 {
-    const double lbar = lc + (double)lbo;  // area-weighted mean depth
     plane_split<T>(T(za), kLo, kHi, v0dv, nv, pha, paa);
     plane_split<T>(T(zb), kLo, kHi, v0dv, nv, phb, pab);
-    const T cA = cT * S.A;
     const int n = pab - paa;      // >= 0: zb > za
     const int qa = min(paa, nv);  // a plane index even when n = 0 and a = nv + 1
-    T alpha = S.A * T(ptau[qa] * lbar - za);
+    T alpha = S.A * T(ptau[qa] * lc - za);
     alpha = n > 0 ? alpha : T(0);
-    const T beta = S.A * T(dtau * lbar);
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) {
         const T *Yb = Y + b * ystride;
         const T ye = Yb[pab - 1];
         T d = n >= 2 ? Yb[qa] - ye : T(0);
         for (int q = paa + 1; q < pab - 1; ++q) d += Yb[q] - ye;
-        sum[b] = fma(cA, ye, fma(alpha, Yb[qa - 1] - ye, beta * d));
+        sum[b] = fma(cA, ye, fma(alpha, Yb[qa - 1] - ye, bA * d));
     }
 }
 
@@ -601,14 +602,14 @@ __host__ __device__ inline int adj_straddle(int t, int na, int pha, int phb, con
 // One strip record's contribution to voxel [za, zb] of its column in the
 // adjoint: sum_q (K_q(za) - K_q(zb)) (y[q-1] - y[q]) with y[-1] = y[nv] = 0.
 template <typename T, int NBAT>
-__host__ __device__ inline void adj_terms(const StripTab<T> &S, double lc, T lbo, T kLo, T kHi,
-                                          const double *ptau, double dtau, const T *ptf,
-                                          const T *pinv, double za, double zb, T v0dv, int nv, T cT,
-                                          const T *Y, size_t ystride, T (&sum)[NBAT])
+__host__ __device__ inline void adj_terms(const StripTab<T> &S, double lc, T cA, T bA, T kLo,
+                                          T kHi, const double *ptau, const T *ptf, const T *pinv,
+                                          double za, double zb, T v0dv, int nv, const T *Y,
+                                          size_t ystride, T (&sum)[NBAT])
 {
     int pha, paa, phb, pab;
-    adj_lin<T, NBAT>(S, lc, lbo, kLo, kHi, ptau, dtau, za, zb, v0dv, nv, cT, Y, ystride, pha, paa,
-                     phb, pab, sum);
+    adj_lin<T, NBAT>(S, lc, cA, bA, kLo, kHi, ptau, za, zb, v0dv, nv, Y, ystride, pha, paa, phb,
+                     pab, sum);
     const int na = max(paa - pha, 0);
     const int nb = max(pab - phb, 0);
     for (int t = 0; t < na + nb; ++t) {

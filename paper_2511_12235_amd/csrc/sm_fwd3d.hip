@@ -12,11 +12,12 @@
 // voxel faces z_j, G_p = sum_j K_p(z_j) (x_j - x_{j-1}) over the faces from
 // z_f up, K_p(z) the volume of the strip column above z and below plane p
 // (sm_common.h).  Face z_f lies wholly below the plane, so K_p(z_f) is the
-// linear volume A (tau lbar - z_f); faces the plane straddles need the chord
-// table; faces wholly above it add nothing.  So c A (V_{r+1} - V_r) needs the
-// sum of the voxels between the two planes' first voxels f and f' (one or two
-// at the scanned geometries: a detector row's height at the pixel is about a
-// voxel height), gathered from z-contiguous voxel columns.  Lane r keeps
+// linear volume A (tau lc - z_f), lc the strip's centroid depth; faces the
+// plane straddles need the chord table; faces wholly above it add nothing.
+// So c A (V_{r+1} - V_r) needs the sum of the voxels between the two planes'
+// first voxels f and f' (one or two at the scanned geometries: a detector
+// row's height at the pixel is about a voxel height), gathered from
+// z-contiguous voxel columns.  Lane r keeps
 // c A (range sum) - G_r and G_r apart; the G of the plane above is added once
 // at the end through LDS.  The top detector edge (plane nv) has no lane: its
 // G is summed lane-parallel over the strip's pixels in a fixed order.
@@ -68,7 +69,7 @@ __device__ __forceinline__ void fwd_flush(const DevGeom &G, const unsigned char 
         const int e = (int)(jb & 63u), q = (int)((jb >> 6) & 2047u), j = (int)((jb >> 17) & 2047u);
         const Rec<T> &R = lds_rec<T>(rbuf, e);
         const T ev = T(ptau[q] * R.lc - (G.z0 + (double)j * G.c));
-        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab, R.M1), ptf[q], pinv[q], ev);
+        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev);
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) {
             const T *Xc = X + ((size_t)R.pix * B + b0 + b) * nz;
@@ -116,7 +117,7 @@ __device__ __forceinline__ void fwd_flush_fixed(const DevGeom &G, const unsigned
         const int e = (int)(jb & 63u), q = (int)((jb >> 6) & 2047u), j = (int)((jb >> 17) & 2047u);
         const Rec<T> &R = lds_rec<T>(rbuf, e);
         const T ev = T(ptau[q] * R.lc - (G.z0 + (double)j * G.c));
-        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab, R.M1), ptf[q], pinv[q], ev);
+        const T K = K_cut<T>(strip_tab<T>(R.tab, R.tab), ptf[q], pinv[q], ev);
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) {
             const T *Xc = X + ((size_t)R.pix * B + b0 + b) * nz;
@@ -178,7 +179,6 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     const int n_ent = soff[strip * (RL.n_major_max + 1) + ax.n_major];
     const Rec<T> *Rs = recs + strip * RL.cap;
     const T inv_c = T(1.0 / G.c), z0c = T(G.z0 / G.c);
-    const T cT = T(G.c);
 
     // lane r: plane r is the lower edge of row r (lanes past nv carry tau = 0
     // and queue nothing)
@@ -286,11 +286,10 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             const Rec<T> &R = Rs[c0 + e];  // uniform fields through the scalar cache
             const int n = R.n;
             if (n == 0) continue;
-            const StripTab<T> S = strip_tab<T>(R.tab, lds_rec<T>(rbuf, e).tab, R.M1);
+            const StripTab<T> S = strip_tab<T>(R.tab, lds_rec<T>(rbuf, e).tab);
             const double lc = R.lc;
-            const double lbar = lc + (double)R.lbo;
-            const T cA = cT * S.A;
-            const T Klin = S.A * T(tau0 * lbar - (G.z0 + (double)f * G.c));
+            const T cA = R.cA;
+            const T Klin = S.A * T(tau0 * lc - (G.z0 + (double)f * G.c));
             const bool lin = fa >= 1 && fa <= nz;  // then f = fa - 1 < nz
             // voxels f .. f1 - 1 lie between the two planes' first voxels
             T rs[NBAT];
@@ -356,16 +355,15 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             const Rec<T> &R = lds_rec<T>(rbuf, tid);
             const int n = R.n;
             if (n > 0) {
-                const StripTab<T> S = strip_tab<T>(R.tab, R.tab, R.M1);
+                const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
                 const double lc = R.lc;
                 const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
-                const double lbar = lc + (double)R.lbo;
                 const T *Xc[NBAT];
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) Xc[b] = X + ((size_t)R.pix * B + b0 + b) * nz;
                 int f;
                 T gs[NBAT];
-                plane_G<T, NBAT>(G, S, lc, lbar, Llo, Lhi, tauT, tfT, invT, inv_c, z0c, Xc, f, gs);
+                plane_G<T, NBAT>(G, S, lc, Llo, Lhi, tauT, tfT, invT, inv_c, z0c, Xc, f, gs);
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) accT[b] += gs[b];
             }
