@@ -60,18 +60,20 @@ constexpr int MAXV = 6;  // vertices of a strip polygon (rectangle cut by two li
 // the breakpoints in ascending depth, S0 = integral of w beyond the depth,
 // S1 = first moment of w beyond the depth about the depth itself.  Area A =
 // tab[0][2].  The header also holds the row-plane index scales D / (L dv) at
-// the nearest and farthest depth L (see plane_split), c A and A lc dv / D
-// (the step of the linear volume A (tau lc - z) from one row plane to the
-// next), all computed in FP64.  128 bytes for T = float, 240 for T = double.
+// the nearest and farthest depth L (see plane_split), the same two depths in
+// voxel heights (see plane_faces), c A and A lc dv / D (the step of the linear
+// volume A (tau lc - z) from one row plane to the next), all computed in FP64.
+// 144 bytes for T = float, 256 for T = double.
 template <typename T>
 struct alignas(16) Rec {
     double lc;  // depth of the centroid
     int n;      // number of breakpoints, 0 when the polygon is empty
     int pix;    // pixel index iy * nx + ix
     T kLo, kHi; // D / (Llo dv), D / (Lhi dv)
+    T hLo, hHi; // Llo / c, Lhi / c
     T cA;       // c A
     T bA;       // A lc dv / D
-    T tab[MAXV][4];
+    alignas(16) T tab[MAXV][4];
 };
 
 // Stride of a strip record staged in LDS.  Lanes that gather different
@@ -193,6 +195,8 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
     R.lc = lc;
     R.kLo = T(0);
     R.kHi = T(0);
+    R.hLo = T(0);
+    R.hHi = T(0);
     R.cA = T(0);
     R.bA = T(0);
     if (m < 3) {
@@ -277,6 +281,9 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
         R.lc = lc + lbo;
         R.kLo = T(qdiv_(Ddv, lc + bd[0]));
         R.kHi = T(qdiv_(Ddv, lc + dlast));
+        const double rc = qdiv_(1.0, G.c);  // the same for every record: hoisted
+        R.hLo = T((lc + bd[0]) * rc);
+        R.hHi = T((lc + dlast) * rc);
         R.cA = T(G.c * S0[0]);
         R.bA = T(S0[0] * qdiv_(G.dv, G.D) * R.lc);
     }
@@ -361,7 +368,7 @@ __host__ __device__ inline T eval_K(const T (*tab)[4], int n, T tau, T inv_tau, 
 // ---------------------------------------------------------------------------
 // Over the strip, plane z = tau l spans heights [lo, hi] with
 // lo = tau Llo, hi = tau Lhi for tau >= 0 (swapped for tau < 0), Llo / Lhi
-// being the nearest / farthest depth of the strip polygon.  Against a face at
+// being the nearest / farthest depth of the strip polygon (absolute depths).  Against a face at
 // height z a plane is wholly below (K = 0), wholly above (K = the linear
 // integral A (tau lc - z), lc the centroid depth of the strip) or straddles
 // it (K from the chord table).  Both walks below only need the split to be
@@ -400,13 +407,17 @@ __host__ __device__ inline void plane_split(T z, T kLo, T kHi, T v0dv, int nv, i
     pa = (int)fl;
 }
 
-// Voxel faces z_j = z0 + j c against one plane of extent [lo, hi]: faces
-// < fa lie wholly below the plane, faces >= fb wholly above it.
+// Voxel faces z_j = z0 + j c against plane tau over the strip, whose nearest
+// and farthest depths in voxel heights are hLo = Llo / c and hHi = Lhi / c
+// (z0c = z0 / c): faces < fa lie wholly below the plane, faces >= fb wholly
+// above it.  The plane's heights over the strip in voxel heights are tau hLo
+// and tau hHi, so each end of the range takes one multiply-add.
 template <typename T>
-__host__ __device__ inline void face_split(T lo, T hi, T inv_c, T z0c, int nz, int &fa, int &fb)
+__host__ __device__ inline void plane_faces(T tau, T hLo, T hHi, T z0c, int nz, int &fa, int &fb)
 {
+    const bool up = tau >= T(0);
     const T top = T(nz + 1);
-    T a = floor(lo * inv_c - z0c) + T(1), b = ceil(hi * inv_c - z0c);
+    T a = floor(fma(tau, up ? hLo : hHi, -z0c)) + T(1), b = ceil(fma(tau, up ? hHi : hLo, -z0c));
     a = clamp0(a, top);
     b = clamp0(b, top);
     fa = (int)a;
@@ -469,15 +480,6 @@ __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
     return tau < T(0) ? kp + e * S.A : kp;
 }
 
-// Heights of plane tau over the strip [Llo, Lhi] (depths).
-template <typename T>
-__host__ __device__ inline void plane_extent(T tau, T Llo, T Lhi, T &lo, T &hi)
-{
-    const T a = tau * Llo, b = tau * Lhi;
-    lo = tau >= T(0) ? a : b;
-    hi = tau >= T(0) ? b : a;
-}
-
 // The part of G_p of one plane for one strip record that needs no chord
 // table: the linear volume at face f = fa - 1 (the first voxel not wholly
 // below the plane).  Faces fa .. je are straddled (empty when je < fa); their
@@ -485,15 +487,13 @@ __host__ __device__ inline void plane_extent(T tau, T Llo, T Lhi, T &lo, T &hi)
 // of batch element b.
 template <typename T, int NBAT>
 __host__ __device__ inline void plane_lin(const DevGeom &G, const StripTab<T> &S, double lc,
-                                          T Llo, T Lhi, double tau, T tauf, T inv_c, T z0c,
+                                          T hLo, T hHi, double tau, T tauf, T z0c,
                                           const T *const (&Xc)[NBAT], int &f_out, int &fa_out,
                                           int &je_out, T (&gs)[NBAT])
 {
     const int nz = G.nz;
-    T lo, hi;
-    plane_extent<T>(tauf, Llo, Lhi, lo, hi);
     int fa, fb;
-    face_split<T>(lo, hi, inv_c, z0c, nz, fa, fb);
+    plane_faces<T>(tauf, hLo, hHi, z0c, nz, fa, fb);
     const int f = max(fa - 1, 0);  // fa <= nz + 1
     f_out = f;
     fa_out = fa;
@@ -526,11 +526,11 @@ __host__ __device__ inline void straddle_term(const DevGeom &G, const StripTab<T
 // G_p of one plane for one strip record; f_out = first voxel not wholly below.
 template <typename T, int NBAT>
 __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, double lc,
-                                        T Llo, T Lhi, double tau, T tauf, T invt, T inv_c, T z0c,
+                                        T hLo, T hHi, double tau, T tauf, T invt, T z0c,
                                         const T *const (&Xc)[NBAT], int &f_out, T (&gs)[NBAT])
 {
     int fa, je;
-    plane_lin<T, NBAT>(G, S, lc, Llo, Lhi, tau, tauf, inv_c, z0c, Xc, f_out, fa, je, gs);
+    plane_lin<T, NBAT>(G, S, lc, hLo, hHi, tau, tauf, z0c, Xc, f_out, fa, je, gs);
     for (int j = fa; j <= je; ++j) {
         T t[NBAT];
         straddle_term<T, NBAT>(G, S, lc, tau, tauf, invt, j, Xc, t);

@@ -178,7 +178,7 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     const int64_t strip = (int64_t)vl * G.nu + k;
     const int n_ent = soff[strip * (RL.n_major_max + 1) + ax.n_major];
     const Rec<T> *Rs = recs + strip * RL.cap;
-    const T inv_c = T(1.0 / G.c), z0c = T(G.z0 / G.c);
+    const T z0c = T(G.z0 / G.c);
 
     // lane r: plane r is the lower edge of row r (lanes past nv carry tau = 0
     // and queue nothing)
@@ -239,19 +239,12 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
         // an empty record stay in range and are not used)
         auto faces = [&](int e, int &fa, int &je, int &f, int &f1) {
             const Rec<T> &R = Rs[c0 + e];
-            const int n = R.n > 0 ? R.n : 1;
-            const double lc = R.lc;
-            const T Llo = T(lc + (double)R.tab[0][0]), Lhi = T(lc + (double)R.tab[n - 1][0]);
-            T lo, hi;
-            plane_extent<T>(tf0, Llo, Lhi, lo, hi);
             int fb;
-            face_split<T>(lo, hi, inv_c, z0c, nz, fa, fb);
+            plane_faces<T>(tf0, R.hLo, R.hHi, z0c, nz, fa, fb);
             f = max(fa - 1, 0);
             je = fb - 1 < nz ? fb - 1 : nz;
-            T lo1, hi1;
-            plane_extent<T>(tf1, Llo, Lhi, lo1, hi1);
             int fa1, fb1;
-            face_split<T>(lo1, hi1, inv_c, z0c, nz, fa1, fb1);
+            plane_faces<T>(tf1, R.hLo, R.hHi, z0c, nz, fa1, fb1);
             f1 = max(fa1 - 1, 0);
         };
         // x_f and x_{f+1} of the next record (f <= nz, so f + 1 is clamped)
@@ -357,13 +350,12 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             if (n > 0) {
                 const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
                 const double lc = R.lc;
-                const T Llo = T(lc + (double)S.d0), Lhi = T(lc + (double)R.tab[n - 1][0]);
                 const T *Xc[NBAT];
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) Xc[b] = X + ((size_t)R.pix * B + b0 + b) * nz;
                 int f;
                 T gs[NBAT];
-                plane_G<T, NBAT>(G, S, lc, Llo, Lhi, tauT, tfT, invT, inv_c, z0c, Xc, f, gs);
+                plane_G<T, NBAT>(G, S, lc, R.hLo, R.hHi, tauT, tfT, invT, z0c, Xc, f, gs);
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) accT[b] += gs[b];
             }
