@@ -42,16 +42,32 @@ __device__ int block_scan_excl(int v, int *tmp, int &total)
 
 // Four waves per SIMD: the FP64 polygon work is written one edge at a time so
 // that it fits 128 registers; with fewer waves the kernel idles on latency.
+//
+// Records leave through LDS: each lane puts its record's 16-byte chunks in
+// its own column of `stage` (the vertex scratch, free again once the record
+// is built), and the wave then stores its records' chunks in address order,
+// 64 consecutive chunks per instruction, instead of every lane storing one
+// chunk of its own record per instruction (64 partial lines each time).
+// FP64 records (16 chunks) go out in two passes of 8.
+constexpr int kStageRows = 9;
+
 template <typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 rec_kernel(DevGeom G, RecLayout RL, int v0, Rec<T> *__restrict__ recs, int *__restrict__ sj0,
            int *__restrict__ soff, int2 *__restrict__ pixk)
 {
+    constexpr int RCH = (int)(sizeof(Rec<T>) / 16);           // chunks per record
+    constexpr int NPASS = (RCH + kStageRows - 1) / kStageRows;  // staging passes
+    constexpr int PCH = RCH / NPASS;                            // chunks per pass
+    static_assert(PCH * NPASS == RCH && PCH <= kStageRows, "record chunks per pass");
     __shared__ int offs[257];
     __shared__ int jst[256];
     __shared__ int scan_tmp[8];
-    __shared__ double2 wsp[8][256];  // vertex i of thread t at [i][t]: no bank conflicts
+    // vertex i of thread t at [i][t] (no bank conflicts); later chunk c of
+    // thread t's record at [c][t]
+    __shared__ uint4 stage[kStageRows][256];
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wbase = tid - lane;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int vl = lb / G.nu, k = lb - vl * G.nu;
     const int view = v0 + vl;
@@ -62,7 +78,7 @@ rec_kernel(DevGeom G, RecLayout RL, int v0, Rec<T> *__restrict__ recs, int *__re
     const int64_t strip = (int64_t)vl * G.nu + k;
     int *J0 = sj0 + strip * RL.n_major_max;
     int *OFF = soff + strip * (RL.n_major_max + 1);
-    Rec<T> *out = recs + strip * RL.cap;
+    uint4 *out = reinterpret_cast<uint4 *>(recs + strip * RL.cap);
     int2 *pk = pixk + (int64_t)vl * G.nx * G.ny;
 
     int run = 0;  // entries written by earlier chunks of majors
@@ -83,27 +99,56 @@ rec_kernel(DevGeom G, RecLayout RL, int v0, Rec<T> *__restrict__ recs, int *__re
             OFF[im] = run + ex;
         }
         __syncthreads();
-        for (int e = tid; e < total; e += nthr) {
-            int lo = 0, hi = nthr;  // largest m with offs[m] <= e
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (offs[mid] <= e) lo = mid; else hi = mid;
-            }
-            const int mj = base + lo;
-            const int mn = jst[lo] + (e - offs[lo]);
-            const int ix = ax.major_x ? mj : mn;
-            const int iy = ax.major_x ? mn : mj;
-            const int slot = run + e;
-            if (slot < RL.cap) {
-                Rec<T> R;
-                build_record<T>(G, cp, sp, ix, iy, k, R, LdsVerts{&wsp[0][tid], 256});
+        // entries that get a slot: e < total and run + e < cap
+        const int nrec = min(total, RL.cap - run);
+        for (int e0 = 0; e0 < nrec; e0 += nthr) {
+            const int e = e0 + tid;
+            Rec<T> R;
+            if (e < nrec) {
+                int lo = 0, hi = nthr;  // largest m with offs[m] <= e
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (offs[mid] <= e) lo = mid; else hi = mid;
+                }
+                const int mj = base + lo;
+                const int mn = jst[lo] + (e - offs[lo]);
+                const int ix = ax.major_x ? mj : mn;
+                const int iy = ax.major_x ? mn : mj;
+                build_record<T>(G, cp, sp, ix, iy, k, R,
+                                LdsVerts{reinterpret_cast<double2 *>(&stage[0][tid]), 256});
                 R.pix = iy * G.nx + ix;
-                out[slot] = R;
                 if (R.n > 0) {
                     atomicMin(&pk[R.pix].x, k);
                     atomicMax(&pk[R.pix].y, k);
                 }
             }
+            // this wave's records: slots run + e0 + wbase + r, r < nw
+            const int nw = min(max(nrec - e0 - wbase, 0), 64);
+            uint4 *dst = out + (int64_t)(run + e0 + wbase) * RCH;
+            const uint4 *rc = reinterpret_cast<const uint4 *>(&R);
+#pragma unroll
+            for (int ps = 0; ps < NPASS; ++ps) {
+                // the vertex scratch (or the previous pass) of every lane of
+                // the wave is consumed before it is overwritten
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (e < nrec) {
+#pragma unroll
+                    for (int c = 0; c < PCH; ++c) stage[c][tid] = rc[ps * PCH + c];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int q = lane; q < nw * PCH; q += 64) {
+                    const int r = q / PCH, c = q - r * PCH;
+                    dst[(int64_t)r * RCH + ps * PCH + c] = stage[c][wbase + r];
+                }
+            }
+            // the next round's vertex scratch overwrites the staged chunks
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         run += total;
         __syncthreads();
