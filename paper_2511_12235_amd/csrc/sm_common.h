@@ -411,13 +411,15 @@ __host__ __device__ inline void plane_split(T z, T kLo, T kHi, T v0dv, int nv, i
 // and farthest depths in voxel heights are hLo = Llo / c and hHi = Lhi / c
 // (z0c = z0 / c): faces < fa lie wholly below the plane, faces >= fb wholly
 // above it.  The plane's heights over the strip in voxel heights are tau hLo
-// and tau hHi, so each end of the range takes one multiply-add.
+// and tau hHi, so each end of the range takes one multiply-add; their order
+// follows the sign of tau, which a min and a max settle without a select
+// (rounding is monotone, so they pick the same values a select would).
 template <typename T>
 __host__ __device__ inline void plane_faces(T tau, T hLo, T hHi, T z0c, int nz, int &fa, int &fb)
 {
-    const bool up = tau >= T(0);
     const T top = T(nz + 1);
-    T a = floor(fma(tau, up ? hLo : hHi, -z0c)) + T(1), b = ceil(fma(tau, up ? hHi : hLo, -z0c));
+    const T e0 = fma(tau, hLo, -z0c), e1 = fma(tau, hHi, -z0c);
+    T a = floor(fmin(e0, e1)) + T(1), b = ceil(fmax(e0, e1));
     a = clamp0(a, top);
     b = clamp0(b, top);
     fa = (int)a;

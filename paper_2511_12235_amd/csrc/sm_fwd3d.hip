@@ -248,14 +248,17 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
             f1 = max(fa1 - 1, 0);
         };
         // x_f and x_{f+1} of the next record (f <= nz, so f + 1 is clamped)
+        // (32-bit byte offsets from the column's uniform base: one shift
+        // per gather instead of a 64-bit address)
         auto gather = [&](int e, int f, T (&xa)[NBAT], T (&xb)[NBAT]) {
             const int pix = Rs[c0 + e].pix;
-            const int ia = f < nz ? f : nz - 1, ib = f + 1 < nz ? f + 1 : nz - 1;
+            const unsigned oa = (unsigned)(f < nz ? f : nz - 1) * (unsigned)sizeof(T);
+            const unsigned ob = (unsigned)(f + 1 < nz ? f + 1 : nz - 1) * (unsigned)sizeof(T);
 #pragma unroll
             for (int b = 0; b < NBAT; ++b) {
-                const T *Xn = X + ((size_t)pix * B + b0 + b) * nz;
-                xa[b] = Xn[ia];
-                xb[b] = Xn[ib];
+                const char *Xn = reinterpret_cast<const char *>(X + ((size_t)pix * B + b0 + b) * nz);
+                xa[b] = *reinterpret_cast<const T *>(Xn + oa);
+                xb[b] = *reinterpret_cast<const T *>(Xn + ob);
             }
         };
         int nfa = 0, nje = 0, nf = 0, nf1 = 0;

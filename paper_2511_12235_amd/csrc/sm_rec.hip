@@ -50,6 +50,10 @@ __device__ int block_scan_excl(int v, int *tmp, int &total)
 // chunk of its own record per instruction (64 partial lines each time).
 // FP64 records (16 chunks) go out in two passes of 8.
 constexpr int kStageRows = 9;
+// Row stride of `stage` in 16-byte elements: one more than the threads, so
+// that the chunks one store instruction gathers (several chunks of each of
+// a few records) fall in different LDS banks.
+constexpr int kStageStride = 257;
 
 template <typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
@@ -65,7 +69,7 @@ rec_kernel(DevGeom G, RecLayout RL, int v0, Rec<T> *__restrict__ recs, int *__re
     __shared__ int scan_tmp[8];
     // vertex i of thread t at [i][t] (no bank conflicts); later chunk c of
     // thread t's record at [c][t]
-    __shared__ uint4 stage[kStageRows][256];
+    __shared__ uint4 stage[kStageRows][kStageStride];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63, wbase = tid - lane;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -115,7 +119,7 @@ rec_kernel(DevGeom G, RecLayout RL, int v0, Rec<T> *__restrict__ recs, int *__re
                 const int ix = ax.major_x ? mj : mn;
                 const int iy = ax.major_x ? mn : mj;
                 build_record<T>(G, cp, sp, ix, iy, k, R,
-                                LdsVerts{reinterpret_cast<double2 *>(&stage[0][tid]), 256});
+                                LdsVerts{reinterpret_cast<double2 *>(&stage[0][tid]), kStageStride});
                 R.pix = iy * G.nx + ix;
                 if (R.n > 0) {
                     atomicMin(&pk[R.pix].x, k);
