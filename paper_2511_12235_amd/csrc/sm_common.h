@@ -391,6 +391,26 @@ __host__ __device__ inline float clamp0(float v, float top)
 }
 __host__ __device__ inline double clamp0(double v, double top) { return fmin(fmax(v, 0.0), top); }
 
+// floor(v) + 1 clamped to [0, top] (top an integer), as an int.  FP32 on the
+// device: clamp to [-1, top - 1] first (same result, and the conversion stays
+// in range), then one floor-and-convert instruction, which the compiler does
+// not form from floor and a conversion; three instructions instead of four.
+// (The forward's face splits use it; in the adjoint's plane splits the
+// opaque instruction cost the kernel 4 VGPRs and its 6 waves per SIMD.)
+__host__ __device__ inline int floor1_clamp(float v, float top)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float c = __builtin_amdgcn_fmed3f(v, -1.0f, top - 1.0f);
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(c));
+    return r + 1;
+#else
+    const float a = floorf(v) + 1.0f;
+    return (int)(a < 0.0f ? 0.0f : (a > top ? top : a));
+#endif
+}
+__host__ __device__ inline int floor1_clamp(double v, double top) { return (int)clamp0(floor(v) + 1.0, top); }
+
 // Row planes: indices < ph lie wholly below z, indices >= pa wholly above.
 // tau_q = (v0 + q dv) / D, kLo = D / (Llo dv), kHi = D / (Lhi dv).
 template <typename T>
@@ -419,11 +439,8 @@ __host__ __device__ inline void plane_faces(T tau, T hLo, T hHi, T z0c, int nz, 
 {
     const T top = T(nz + 1);
     const T e0 = fma(tau, hLo, -z0c), e1 = fma(tau, hHi, -z0c);
-    T a = floor(fmin(e0, e1)) + T(1), b = ceil(fmax(e0, e1));
-    a = clamp0(a, top);
-    b = clamp0(b, top);
-    fa = (int)a;
-    fb = (int)b;
+    fa = floor1_clamp(T(fmin(e0, e1)), top);
+    fb = (int)clamp0(T(ceil(fmax(e0, e1))), top);
 }
 
 // The uniform part of a strip record used by K_cut; `tab` points at the
