@@ -137,22 +137,20 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
     const int nz = G.nz, nv = G.nv;
     const int rowstride = nv + 2;
 
-    // LDS: staged records | plane tables | detector patch
+    // LDS: staged records | plane table | detector patch
     Rec<T> *rtab = reinterpret_cast<Rec<T> *>(smem);
-    size_t off = sizeof(Rec<T>) * (size_t)TP * rspan;
-    double *ptau = reinterpret_cast<double *>(smem + off);
-    off += sizeof(double) * (nv + 1);
-    T *ptf = reinterpret_cast<T *>(smem + off);
-    T *pinv = ptf + (nv + 1);
-    off += 2 * sizeof(T) * (nv + 1);
-    off = (off + 15) & ~(size_t)15;
+    size_t off = sizeof(Rec<T>) * (size_t)TP * rspan;  // a multiple of 16
+    PlaneRow<T> *prow = reinterpret_cast<PlaneRow<T> *>(smem + off);
+    off += sizeof(PlaneRow<T>) * (nv + 1);
     T *patch = reinterpret_cast<T *>(smem + off);
 
     for (int p = tid; p <= nv; p += nthr) {
         const double t = G.tau[p];
-        ptau[p] = t;
-        ptf[p] = T(t);
-        pinv[p] = t != 0.0 ? T(1) / T(t) : T(0);
+        PlaneRow<T> row;
+        row.tau = t;
+        row.tf = T(t);
+        row.inv = t != 0.0 ? T(1) / T(t) : T(0);
+        prow[p] = row;
     }
 
     const int ntx = (G.nx + TX - 1) / TX, nty = (G.ny + TY - 1) / TY;
@@ -215,7 +213,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
                 const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
                 const T *Y = patch + (size_t)(k - kmin) * rowstride + 1;  // Y[-1] .. Y[nv]
                 T sum[NBAT];
-                adj_terms<T, NBAT>(S, R.lc, R.cA, R.bA, R.kLo, R.kHi, ptau, ptf, pinv, za, zb, v0dv,
+                adj_terms<T, NBAT>(S, R.lc, R.cA, R.bA, R.kLo, R.kHi, prow, za, zb, v0dv,
                                    nv, Y, (size_t)pcols * rowstride, sum);
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) cur[b] += sum[b];
@@ -249,8 +247,7 @@ template <typename T, int NBAT, int TX, int TY>
 static size_t back3d_lds(const DevGeom &G, const LaunchCfg &L, int slot)
 {
     size_t lds = sizeof(Rec<T>) * (size_t)TX * TY * L.rspan;
-    lds += sizeof(double) * (G.nv + 1) + 2 * sizeof(T) * (G.nv + 1);
-    lds = (lds + 15) & ~(size_t)15;
+    lds += sizeof(PlaneRow<T>) * (G.nv + 1);
     lds += sizeof(T) * (size_t)NBAT * L.back_pcols[slot] * (G.nv + 2);
     return lds;
 }

@@ -558,14 +558,23 @@ __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, 
     }
 }
 
+// Row plane q in the adjoint's LDS table: its slope in FP64 (for face
+// heights), in T and the inverse in T (for K_cut), side by side so that one
+// address and one wide read serve a straddle term.
+template <typename T>
+struct alignas(16) PlaneRow {
+    double tau;
+    T tf, inv;
+};
+
 // The part of one strip record's contribution to voxel [za, zb] of its column
 // in the adjoint that needs no chord table: c A y[pab - 1] for the planes
 // wholly above the voxel plus the linear volumes at za of the planes wholly
 // above za that reach below zb.  Planes pha .. paa - 1 straddle za and
 // phb .. pab - 1 straddle zb (adj_straddle gives their terms).
 // Y[b * ystride + q] holds y[q] of batch element b for q in [-1, nv];
-// ptau holds the plane slopes in FP64; cA = c A and bA = A lc dv / D come
-// with the record.
+// pl holds the plane slopes; cA = c A and bA = A lc dv / D come with the
+// record.
 //
 // The linear volumes are K_q = A (tau_q lc - za) = alpha + (q - a) bA for
 // q = a .. e - 1 (a = paa, e = pab; the slopes tau_q are dv / D apart), with
@@ -579,7 +588,7 @@ __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, 
 // volume's result does not depend on the batch it is applied in.
 template <typename T, int NBAT>
 __host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T cA, T bA, T kLo, T kHi,
-                                        const double *ptau, double za, double zb, T v0dv, int nv,
+                                        const PlaneRow<T> *pl, double za, double zb, T v0dv, int nv,
                                         const T *Y, size_t ystride, int &pha, int &paa, int &phb,
                                         int &pab, T (&sum)[NBAT])
 {
@@ -587,7 +596,7 @@ __host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T cA, T
     plane_split<T>(T(zb), kLo, kHi, v0dv, nv, phb, pab);
     const int n = pab - paa;      // >= 0: zb > za
     const int qa = min(paa, nv);  // a plane index even when n = 0 and a = nv + 1
-    T alpha = S.A * T(ptau[qa] * lc - za);
+    T alpha = S.A * T(pl[qa].tau * lc - za);
     alpha = n > 0 ? alpha : T(0);
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) {
@@ -603,13 +612,13 @@ __host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T cA, T
 // phb + t - na at zb, subtracted): the plane q, the face height e and the
 // signed row differences; the term is K_cut(e) * dY.
 template <typename T, int NBAT>
-__host__ __device__ inline int adj_straddle(int t, int na, int pha, int phb, const double *ptau,
+__host__ __device__ inline int adj_straddle(int t, int na, int pha, int phb, const PlaneRow<T> *pl,
                                             double lc, double za, double zb, const T *Y,
                                             size_t ystride, T &e, T (&dY)[NBAT])
 {
     const bool top = t >= na;
     const int q = (top ? phb - na : pha) + t;
-    e = T(ptau[q] * lc - (top ? zb : za));
+    e = T(pl[q].tau * lc - (top ? zb : za));
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) {
         const T d = Y[b * ystride + q - 1] - Y[b * ystride + q];
@@ -622,19 +631,19 @@ __host__ __device__ inline int adj_straddle(int t, int na, int pha, int phb, con
 // adjoint: sum_q (K_q(za) - K_q(zb)) (y[q-1] - y[q]) with y[-1] = y[nv] = 0.
 template <typename T, int NBAT>
 __host__ __device__ inline void adj_terms(const StripTab<T> &S, double lc, T cA, T bA, T kLo,
-                                          T kHi, const double *ptau, const T *ptf, const T *pinv,
+                                          T kHi, const PlaneRow<T> *pl,
                                           double za, double zb, T v0dv, int nv, const T *Y,
                                           size_t ystride, T (&sum)[NBAT])
 {
     int pha, paa, phb, pab;
-    adj_lin<T, NBAT>(S, lc, cA, bA, kLo, kHi, ptau, za, zb, v0dv, nv, Y, ystride, pha, paa, phb,
+    adj_lin<T, NBAT>(S, lc, cA, bA, kLo, kHi, pl, za, zb, v0dv, nv, Y, ystride, pha, paa, phb,
                      pab, sum);
     const int na = max(paa - pha, 0);
     const int nb = max(pab - phb, 0);
     for (int t = 0; t < na + nb; ++t) {
         T e, dY[NBAT];
-        const int q = adj_straddle<T, NBAT>(t, na, pha, phb, ptau, lc, za, zb, Y, ystride, e, dY);
-        const T K = K_cut<T>(S, ptf[q], pinv[q], e);
+        const int q = adj_straddle<T, NBAT>(t, na, pha, phb, pl, lc, za, zb, Y, ystride, e, dY);
+        const T K = K_cut<T>(S, pl[q].tf, pl[q].inv, e);
 #pragma unroll
         for (int b = 0; b < NBAT; ++b) sum[b] += K * dY[b];
     }
