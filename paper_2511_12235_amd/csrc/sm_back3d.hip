@@ -183,6 +183,8 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
         const StripAxis ax = strip_axis(G, cs.x, cs.y);
         int kmin, kmax;
         if (!tile_columns<TX, TY>(G, pixk, vl, ix0, iy0, pcols, kmin, kmax)) continue;
+        kmin = __builtin_amdgcn_readfirstlane(kmin);  // uniform: keep the column
+        kmax = __builtin_amdgcn_readfirstlane(kmax);  // bounds in scalar registers
         __syncthreads();  // the previous view's patch and records are consumed
         stage_view<T, NBAT, TX, TY, sizeof(Rec<T>)>(G, RL, ax, vl, view, ix0, iy0, kmin, kmax, recs, sj0,
                                                     soff, pixk, y, b0, pcols, rspan,
@@ -197,12 +199,15 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
 #pragma unroll 8
         for (int p = 0; p < TP; ++p) {
             const int ix = ix0 + p % TX, iy = iy0 + p / TX;
-            int k0 = 0, k1 = -1;
-            if (ix < G.nx && iy < G.ny) {
-                const int2 q = pixk[(size_t)vl * npix + (size_t)iy * G.nx + ix];
-                k0 = q.x;
-                k1 = min(min(q.y, q.x + rspan - 1), kmax);  // rspan bounds every pixel's span
-            }
+            // the column range is the same for every lane: scalar registers
+            // and scalar loop control (pixels past the volume's edge read
+            // their clamped neighbour's range and then take an empty one)
+            const bool inside = ix < G.nx && iy < G.ny;
+            const int2 q = pixk[(size_t)vl * npix + (size_t)min(iy, G.ny - 1) * G.nx + min(ix, G.nx - 1)];
+            const int qx = __builtin_amdgcn_readfirstlane(q.x), qy = __builtin_amdgcn_readfirstlane(q.y);
+            const int k0 = inside ? qx : 0;
+            const int k1 = __builtin_amdgcn_readfirstlane(
+                inside ? min(min(qy, qx + rspan - 1), kmax) : -1);  // rspan bounds every span
             T cur[NBAT];
 #pragma unroll
             for (int b = 0; b < NBAT; ++b) cur[b] = acc[0][b];
