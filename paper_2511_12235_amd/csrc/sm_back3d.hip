@@ -281,6 +281,10 @@ static hipError_t launch_back3d_all(const DevGeom &G, const LaunchCfg &L, const 
     const size_t bud = (size_t)L.lds_budget;
     const bool fit4 = back3d_lds<T, 4, 2, 2>(G, L, 2) <= bud;
     const bool fit2 = back3d_lds<T, 2, 4, 2>(G, L, 1) <= bud;
+    // single volumes with two waves per workgroup (nz <= 128) take 4 x 2
+    // tiles: a 4 x 4 tile's staged records and detector patch would hold
+    // such workgroups to about 4.5 waves per SIMD
+    const bool half = back_tile_rows(G) == 2 && back3d_lds<T, 1, 4, 2>(G, L, 1) <= bud;
     hipError_t e = hipSuccess;
     // at most four volumes per launch: eight (2 x 1 tiles) measured slower per
     // volume than two launches of four at 256^3
@@ -288,6 +292,7 @@ static hipError_t launch_back3d_all(const DevGeom &G, const LaunchCfg &L, const 
         const int rem = B - b0;
         if (rem >= 4 && fit4) { e = launch_back3d_t<T, 4, 2, 2>(G, L, RL, 2, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 4; }
         else if (rem >= 2 && fit2) { e = launch_back3d_t<T, 2, 4, 2>(G, L, RL, 1, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 2; }
+        else if (half) { e = launch_back3d_t<T, 1, 4, 2>(G, L, RL, 1, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 1; }
         else { e = launch_back3d_t<T, 1, 4, 4>(G, L, RL, 0, v0, nvc, RP, y, xt, B, b0, first, st); b0 += 1; }
     }
     return e;
@@ -295,6 +300,8 @@ static hipError_t launch_back3d_all(const DevGeom &G, const LaunchCfg &L, const 
 
 size_t back3d_lds_min(const DevGeom &G, const LaunchCfg &L, bool fp64)
 {
+    if (back_tile_rows(G) == 2)
+        return fp64 ? back3d_lds<double, 1, 4, 2>(G, L, 1) : back3d_lds<float, 1, 4, 2>(G, L, 1);
     return fp64 ? back3d_lds<double, 1, 4, 4>(G, L, 0) : back3d_lds<float, 1, 4, 4>(G, L, 0);
 }
 
