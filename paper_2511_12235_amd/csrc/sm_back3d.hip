@@ -284,7 +284,7 @@ static hipError_t launch_back3d_all(const DevGeom &G, const LaunchCfg &L, const 
     // single volumes with two waves per workgroup (nz <= 128) take 4 x 2
     // tiles: a 4 x 4 tile's staged records and detector patch would hold
     // such workgroups to about 4.5 waves per SIMD
-    const bool half = back_tile_rows(G) == 2 && back3d_lds<T, 1, 4, 2>(G, L, 1) <= bud;
+    const bool half = back_tile_rows(G, sizeof(T) == 8) == 2 && back3d_lds<T, 1, 4, 2>(G, L, 1) <= bud;
     hipError_t e = hipSuccess;
     // at most four volumes per launch: eight (2 x 1 tiles) measured slower per
     // volume than two launches of four at 256^3
@@ -300,7 +300,7 @@ static hipError_t launch_back3d_all(const DevGeom &G, const LaunchCfg &L, const 
 
 size_t back3d_lds_min(const DevGeom &G, const LaunchCfg &L, bool fp64)
 {
-    if (back_tile_rows(G) == 2)
+    if (back_tile_rows(G, fp64) == 2)
         return fp64 ? back3d_lds<double, 1, 4, 2>(G, L, 1) : back3d_lds<float, 1, 4, 2>(G, L, 1);
     return fp64 ? back3d_lds<double, 1, 4, 4>(G, L, 0) : back3d_lds<float, 1, 4, 4>(G, L, 0);
 }

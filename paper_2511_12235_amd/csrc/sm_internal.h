@@ -88,9 +88,10 @@ hipError_t launch_back3d(const DevGeom &G, const LaunchCfg &L, const RecLayout &
                          int v0, int nvc, void *ws, const void *y, void *xt, int B, bool first,
                          hipStream_t st);
 // Pixel rows of the single-volume adjoint's tile (4 pixels wide): 2 when its
-// workgroups have two waves or fewer (nz <= 128), whose occupancy the 4 x 4
-// tile's staged records and detector patch would bound, else 4.
-inline int back_tile_rows(const DevGeom &G) { return G.nz <= 128 ? 2 : 4; }
+// workgroups have two waves or fewer (nz <= 128), or in FP64 (256-byte
+// records, 8-byte detector values), whose occupancy the 4 x 4 tile's staged
+// records and detector patch would bound, else 4.
+inline int back_tile_rows(const DevGeom &G, bool fp64) { return G.nz <= 128 || fp64 ? 2 : 4; }
 
 // Whether the smallest forward configuration (single batch element) fits LDS.
 bool fwd3d_fits(const LaunchCfg &L, bool fp64);
