@@ -40,9 +40,15 @@ namespace smk {
 
 // Strip records staged in LDS at a time: 16 per wave of the workgroup, at
 // most 64, so that the LDS of a workgroup stays near 5 KiB per wave and small
-// workgroups (few detector rows) still reach 8 waves per SIMD.
+// workgroups (few detector rows) still reach 8 waves per SIMD.  FP64 records
+// (272 bytes in LDS) stage half as many, so that LDS does not bound the FP64
+// kernel below the waves its registers allow.
 constexpr int kFwdChunkMax = 64;
-__host__ __device__ inline int fwd_chunk(int threads) { return min(kFwdChunkMax, 16 * (threads / 64)); }
+template <typename T>
+__host__ __device__ inline int fwd_chunk(int threads)
+{
+    return sizeof(T) == 4 ? min(kFwdChunkMax, 16 * (threads / 64)) : min(kFwdChunkMax / 2, 8 * (threads / 64));
+}
 
 // Straddle jobs a wave can hold: 128 (evaluated once 64 are pending) or, when
 // LDS is short (many rows), 64 (evaluated before every ballot round); at most
@@ -147,7 +153,7 @@ fwd3d_kernel(DevGeom G, RecLayout RL, int v0, const Rec<T> *__restrict__ recs,
     const int nthr = blockDim.x, tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     // LDS: staged records | per-wave job queues | exchange and reduction arrays
-    const int chunk = fwd_chunk(nthr);
+    const int chunk = fwd_chunk<T>(nthr);
     unsigned char *rbuf = smem;  // chunk records at lds_rec_stride<T>()
     size_t off = lds_rec_stride<T>() * chunk;
     const size_t qbytes = fixed ? (size_t)qcap * sizeof(unsigned)
@@ -410,7 +416,7 @@ static size_t fwd3d_lds(const LaunchCfg &L, int qcap)
     constexpr bool fixed = sizeof(T) == 4;
     const size_t qbytes = fixed ? (size_t)qcap * sizeof(unsigned)
                                 : kRounds * sizeof(JobRound) + (size_t)qcap * (sizeof(unsigned) + sizeof(T) * NBAT);
-    size_t lds = lds_rec_stride<T>() * fwd_chunk(L.fwd_threads) + qbytes * (size_t)(L.fwd_threads / 64);
+    size_t lds = lds_rec_stride<T>() * fwd_chunk<T>(L.fwd_threads) + qbytes * (size_t)(L.fwd_threads / 64);
     // plane tables (nv + 1 <= fwd_threads + 1)
     lds += (sizeof(double) + 2 * sizeof(T)) * (size_t)(L.fwd_threads + 1);
     lds = (lds + 15) & ~(size_t)15;
