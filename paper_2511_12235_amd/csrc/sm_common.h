@@ -560,9 +560,10 @@ __host__ __device__ inline void plane_G(const DevGeom &G, const StripTab<T> &S, 
 
 // Row plane q in the adjoint's LDS table: its slope in FP64 (for face
 // heights), in T and the inverse in T (for K_cut), side by side so that one
-// address and one wide read serve a straddle term.
+// address and one wide read serve a straddle term (16 bytes in FP32; 24 in
+// FP64, where LDS bounds the adjoint's occupancy).
 template <typename T>
-struct alignas(16) PlaneRow {
+struct alignas(sizeof(T) == 4 ? 16 : 8) PlaneRow {
     double tau;
     T tf, inv;
 };
