@@ -368,10 +368,10 @@ __host__ __device__ inline T eval_K(const T (*tab)[4], int n, T tau, T inv_tau, 
 // ---------------------------------------------------------------------------
 // Over the strip, plane z = tau l spans heights [lo, hi] with
 // lo = tau Llo, hi = tau Lhi for tau >= 0 (swapped for tau < 0), Llo / Lhi
-// being the nearest / farthest depth of the strip polygon (absolute depths).  Against a face at
-// height z a plane is wholly below (K = 0), wholly above (K = the linear
-// integral A (tau lc - z), lc the centroid depth of the strip) or straddles
-// it (K from the chord table).  Both walks below only need the split to be
+// being the nearest / farthest (absolute) depth of the strip polygon.
+// Against a face at height z a plane is wholly below (K = 0), wholly above
+// (K = the linear integral A (tau lc - z), lc the centroid depth of the
+// strip) or straddles it (K from the chord table).  Both walks below only need the split to be
 // consistent: K_cut is exact for a sloped plane anywhere, and a plane put on
 // the wrong side of a face by rounding is off by a volume of rounding size.
 // A horizontal plane (tau = 0) spans the single height 0, so both splits put
@@ -479,10 +479,10 @@ template <typename T>
 __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
 {
     const T lam = -e * inv_tau;
-    // row offset in bytes: one select per breakpoint, no shifts
+    // row offset in bytes: the breakpoints at or below lam, counted (the
+    // compiler adds two of the comparisons as carries), times the row size
     constexpr int RB = 4 * (int)sizeof(T);
-    const int jo = (lam >= S.b1 ? RB : 0) + (lam >= S.b2 ? RB : 0) + (lam >= S.b3 ? RB : 0) +
-                   (lam >= S.b4 ? RB : 0);
+    const int jo = RB * ((int)(lam >= S.b1) + (int)(lam >= S.b2) + (int)(lam >= S.b3) + (int)(lam >= S.b4));
     const T *r0 = reinterpret_cast<const T *>(reinterpret_cast<const char *>(S.tab) + jo);
     const T *r1 = r0 + 4;
     const T dA = r0[0], w0 = r0[1];
