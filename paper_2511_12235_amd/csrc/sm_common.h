@@ -490,9 +490,11 @@ __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
     const T L = dB - dA;
     T h = dB - lam;
     h = clamp0(h, L);  // L >= 0: breakpoints ascend
-    // h <= L, so a zero-length segment gives h = 0 and the guard keeps 0 * inf out
-    const T wl = w1 + (w0 - w1) * (h * rcp_(L > T(1e-30) ? L : T(1e-30)));
-    T psi = h * h * (wl * T(1.0 / 6.0) + w1 * T(1.0 / 3.0)) + s1 + h * s0;
+    // Psi = s1 + h s0 + h^2 w1 / 2 + h^3 g / 6 with g the chord width's slope
+    // over the segment, in Horner form.  h <= L, so a zero-length segment
+    // gives h = 0, and the guard keeps g finite there.
+    const T g6 = (w0 - w1) * rcp_(L > T(1e-30) ? L : T(1e-30)) * T(1.0 / 6.0);
+    T psi = fma(h, fma(h, fma(h, g6, w1 * T(0.5)), s0), s1);
     const T below = S.d0 - lam;
     psi += (below > T(0) ? below : T(0)) * S.A;
     const T kp = fabs(tau) * psi;
