@@ -56,10 +56,10 @@ constexpr int MAXV = 6;  // vertices of a strip polygon (rectangle cut by two li
 // Strip record: pixel `pix` cut by detector column k in one view.  Depths
 // l' are measured from lc, the depth of the strip polygon's centroid (its
 // area-weighted mean depth), so that the first moment of the chord width
-// about the origin vanishes.  tab[i] = (depth l', chord width w, S0, S1) for
-// the breakpoints in ascending depth, S0 = integral of w beyond the depth,
-// S1 = first moment of w beyond the depth about the depth itself.  Area A =
-// tab[0][2].  The header also holds the row-plane index scales D / (L dv) at
+// about the origin vanishes.  tab[i] = (depth l', half the chord width w / 2,
+// S0, S1) for the breakpoints in ascending depth, S0 = integral of w beyond
+// the depth, S1 = first moment of w beyond the depth about the depth itself.
+// Area A = tab[0][2].  The header also holds the row-plane index scales D / (L dv) at
 // the nearest and farthest depth L (see plane_split), the same two depths in
 // voxel heights (see plane_faces), c A and A lc dv / D (the step of the linear
 // volume A (tau lc - z) from one row plane to the next), all computed in FP64.
@@ -290,7 +290,7 @@ __host__ __device__ inline void build_record(const DevGeom &G, double cp, double
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
         R.tab[i][0] = T((i < m ? bd[i] : dlast) - lbo);
-        R.tab[i][1] = T(bw[i]);
+        R.tab[i][1] = T(0.5 * bw[i]);  // half the chord width (see K_cut)
         R.tab[i][2] = T(S0[i]);
         R.tab[i][3] = T(S1[i]);
     }
@@ -340,8 +340,8 @@ __host__ __device__ inline T psi_inside(const T (*tab)[4], int n, T lam)
     const T L = d1 - d0;
     T h = d1 - lam;
     h = h < T(0) ? T(0) : (h > L ? L : h);
-    const T wl = w1 + (w0 - w1) * (L > T(0) ? h * rcp_(L) : T(0));
-    return h * h * (wl * T(1.0 / 6.0) + w1 * T(1.0 / 3.0)) + s1 + h * s0;
+    const T wl = w1 + (w0 - w1) * (L > T(0) ? h * rcp_(L) : T(0));  // half widths
+    return h * h * (wl * T(1.0 / 3.0) + w1 * T(2.0 / 3.0)) + s1 + h * s0;
 }
 
 // K = integral over P of (e + tau l')_+ dA: the volume of the column above a
@@ -491,10 +491,11 @@ __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
     T h = dB - lam;
     h = clamp0(h, L);  // L >= 0: breakpoints ascend
     // Psi = s1 + h s0 + h^2 w1 / 2 + h^3 g / 6 with g the chord width's slope
-    // over the segment, in Horner form.  h <= L, so a zero-length segment
-    // gives h = 0, and the guard keeps g finite there.
-    const T g6 = (w0 - w1) * rcp_(L > T(1e-30) ? L : T(1e-30)) * T(1.0 / 6.0);
-    T psi = fma(h, fma(h, fma(h, g6, w1 * T(0.5)), s0), s1);
+    // over the segment, in Horner form; the table holds half widths, so
+    // w1 / 2 is read directly and g / 6 = (w0/2 - w1/2) / (3 L).  h <= L, so
+    // a zero-length segment gives h = 0, and the guard keeps g finite there.
+    const T g6 = (w0 - w1) * rcp_(L > T(1e-30) ? L : T(1e-30)) * T(1.0 / 3.0);
+    T psi = fma(h, fma(h, fma(h, g6, w1), s0), s1);
     const T below = S.d0 - lam;
     psi += (below > T(0) ? below : T(0)) * S.A;
     const T kp = fabs(tau) * psi;
