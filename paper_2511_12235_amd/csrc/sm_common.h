@@ -607,7 +607,9 @@ __host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T cA, T
         const T *Yb = Y + b * ystride;
         const T ye = Yb[pab - 1];
         T d = n >= 2 ? Yb[qa] - ye : T(0);
-        for (int q = paa + 1; q < pab - 1; ++q) d += Yb[q] - ye;
+        if (n >= 3) {  // rare: tested on n, the loop bounds only inside
+            for (int q = paa + 1; q < pab - 1; ++q) d += Yb[q] - ye;
+        }
         sum[b] = fma(cA, ye, fma(alpha, Yb[qa - 1] - ye, bA * d));
     }
 }
