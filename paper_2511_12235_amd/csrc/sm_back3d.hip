@@ -65,10 +65,12 @@ __device__ __forceinline__ void stage_view(const DevGeom &G, const RecLayout &RL
             dst[col * rowstride + nv] = T(0);
         }
     }
-    // strip records: a single volume copies a whole record per thread (one
-    // slot lookup, its registers are free); batches, which hold more sums,
-    // copy one 16-byte chunk per thread
-    constexpr int CPT = NBAT == 1 ? RCH : 1;  // chunks per thread
+    // strip records: a single volume copies part of a record per thread, a
+    // third of an FP32 one (9 chunks) or half an FP64 one (16 chunks), so
+    // that the copy holds few registers in flight (a whole record per thread
+    // set the kernel's register peak); batches, which hold more sums, copy one
+    // 16-byte chunk per thread
+    constexpr int CPT = NBAT != 1 ? 1 : RCH % 2 == 0 ? RCH / 2 : RCH % 3 == 0 ? RCH / 3 : RCH;
     constexpr int TPS = RCH / CPT;            // threads per slot
     const float inv_rspan = 1.0f / (float)rspan;
     for (int q = tid; q < TP * rspan * TPS; q += nthr) {
