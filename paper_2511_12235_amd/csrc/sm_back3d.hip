@@ -24,6 +24,8 @@
 
 namespace smk {
 
+static_assert(sizeof(AdjRec<float>) == 144 && sizeof(AdjRec<double>) == 272, "staged record");
+
 // Stage view `view`'s detector columns kmin .. kmax (pc of them, all rows,
 // zero rows at -1 and nv) and the strip records of the tile's pixels, slot
 // (p, k - k0(p)) at rtab + slot * RS bytes; a slot without a record gets
@@ -37,7 +39,6 @@ __device__ __forceinline__ void stage_view(const DevGeom &G, const RecLayout &RL
                                            unsigned char *rtab, T *patch)
 {
     constexpr int TP = TX * TY;
-    constexpr int RCH = (int)(sizeof(Rec<T>) / 16);  // 16-byte chunks per record
     const int nthr = blockDim.x, tid = threadIdx.x;
     const int nv = G.nv, rowstride = nv + 2, npix = G.nx * G.ny;
     const int pc = kmax - kmin + 1;
@@ -65,20 +66,22 @@ __device__ __forceinline__ void stage_view(const DevGeom &G, const RecLayout &RL
             dst[col * rowstride + nv] = T(0);
         }
     }
-    // strip records: a single volume copies part of a record per thread, a
-    // third of an FP32 one (9 chunks) or half an FP64 one (16 chunks), so
-    // that the copy holds few registers in flight (a whole record per thread
-    // set the kernel's register peak); batches, which hold more sums, copy one
-    // 16-byte chunk per thread
-    constexpr int CPT = NBAT != 1 ? 1 : RCH % 2 == 0 ? RCH / 2 : RCH % 3 == 0 ? RCH / 3 : RCH;
-    constexpr int TPS = RCH / CPT;            // threads per slot
+    // strip records into AdjRec slots, several threads per slot: part 0
+    // copies the fields, the others table rows 1 .. MAXV - 1 (all five per
+    // thread for an FP32 single volume, else one; a whole record per thread
+    // set the kernel's register peak) with the coefficient of the segment
+    // ending at each
+    constexpr int RPT = NBAT == 1 && sizeof(T) == 4 ? MAXV - 1 : 1;  // table rows per thread
+    constexpr int TPS = 1 + (MAXV - 1) / RPT;                        // threads per slot
+    constexpr int RC = (int)(sizeof(T) * 4 / 16);                    // 16-byte chunks per row
+    static_assert((MAXV - 1) % RPT == 0, "table rows per thread");
     const float inv_rspan = 1.0f / (float)rspan;
     for (int q = tid; q < TP * rspan * TPS; q += nthr) {
-        const int pk = q / TPS, ch0 = (q - pk * TPS) * CPT;   // TPS is a constant
+        const int pk = q / TPS, part = q - pk * TPS;          // TPS is a constant
         const int p = (int)(((float)pk + 0.5f) * inv_rspan);  // exact for pk < 16 rspan, rspan <= 2048
         const int kk = pk - p * rspan;
         const int ix = ix0 + p % TX, iy = iy0 + p / TX;
-        uint4 *dst = reinterpret_cast<uint4 *>(rtab + (size_t)(p * rspan + kk) * RS);
+        AdjRec<T> *dst = reinterpret_cast<AdjRec<T> *>(rtab + (size_t)(p * rspan + kk) * RS);
         int pos = -1;
         int64_t strip = 0;
         if (ix < G.nx && iy < G.ny) {
@@ -91,11 +94,39 @@ __device__ __forceinline__ void stage_view(const DevGeom &G, const RecLayout &RL
             }
         }
         if (pos >= 0) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(recs + strip * RL.cap + pos);
+            const Rec<T> &src = recs[strip * RL.cap + pos];
+            if (part == 0) {
+                dst->lc = src.lc;
+                dst->n = src.n;
+                dst->kLo = src.kLo;
+                dst->kHi = src.kHi;
+                dst->cA = src.cA;
+                dst->bA = src.bA;
+                dst->d0 = src.tab[0][0];
+                dst->A = src.tab[0][2];
+            } else {
+                const int r0 = 1 + (part - 1) * RPT;
+                T dp = src.tab[r0 - 1][0], wp = src.tab[r0 - 1][1];
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) dst[ch0 + c] = src[ch0 + c];
-        } else if (ch0 == 0) {
-            dst[0] = make_uint4(0u, 0u, 0u, 0u);  // lc = 0, n = 0
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = r0 + i;
+                    uint4 ch[RC];
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) ch[c] = reinterpret_cast<const uint4 *>(src.tab[r])[c];
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) reinterpret_cast<uint4 *>(dst->seg[r - 1])[c] = ch[c];
+                    const T *row = reinterpret_cast<const T *>(ch);
+                    // g / 6 on segment r - 1: (w_r-1 / 2 - w_r / 2) / (3 L) from
+                    // the table's half widths; the guard keeps it finite on a
+                    // zero-length segment, where h = 0
+                    const T L = row[0] - dp;
+                    dst->g6[r - 1] = (wp - row[1]) * rcp_(L > T(1e-30) ? L : T(1e-30)) * T(1.0 / 3.0);
+                    dp = row[0];
+                    wp = row[1];
+                }
+            }
+        } else if (part == 0) {
+            dst->n = 0;  // an empty slot
         }
     }
 }
@@ -140,8 +171,8 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
     const int rowstride = nv + 2;
 
     // LDS: staged records | plane table | detector patch
-    Rec<T> *rtab = reinterpret_cast<Rec<T> *>(smem);
-    size_t off = sizeof(Rec<T>) * (size_t)TP * rspan;  // a multiple of 16
+    AdjRec<T> *rtab = reinterpret_cast<AdjRec<T> *>(smem);
+    size_t off = sizeof(AdjRec<T>) * (size_t)TP * rspan;  // a multiple of 16
     PlaneRow<T> *prow = reinterpret_cast<PlaneRow<T> *>(smem + off);
     off += sizeof(PlaneRow<T>) * (nv + 1);
     T *patch = reinterpret_cast<T *>(smem + off);
@@ -188,7 +219,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
         kmin = __builtin_amdgcn_readfirstlane(kmin);  // uniform: keep the column
         kmax = __builtin_amdgcn_readfirstlane(kmax);  // bounds in scalar registers
         __syncthreads();  // the previous view's patch and records are consumed
-        stage_view<T, NBAT, TX, TY, sizeof(Rec<T>)>(G, RL, ax, vl, view, ix0, iy0, kmin, kmax, recs, sj0,
+        stage_view<T, NBAT, TX, TY, sizeof(AdjRec<T>)>(G, RL, ax, vl, view, ix0, iy0, kmin, kmax, recs, sj0,
                                                     soff, pixk, y, b0, pcols, rspan,
                                                     reinterpret_cast<unsigned char *>(rtab), patch);
         __syncthreads();
@@ -214,10 +245,10 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
 #pragma unroll
             for (int b = 0; b < NBAT; ++b) cur[b] = acc[0][b];
             for (int k = max(k0, kmin); k <= k1; ++k) {
-                const Rec<T> &R = rtab[p * rspan + (k - k0)];  // LDS copy
+                const AdjRec<T> &R = rtab[p * rspan + (k - k0)];  // LDS copy
                 const int n = __builtin_amdgcn_readfirstlane(R.n);
                 if (n == 0) continue;
-                const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
+                const AdjTab<T> S = adj_tab<T>(R);
                 const T *Y = patch + (size_t)(k - kmin) * rowstride + 1;  // Y[-1] .. Y[nv]
                 T sum[NBAT];
                 adj_terms<T, NBAT>(S, R.lc, R.cA, R.bA, R.kLo, R.kHi, prow, za, zb, v0dv,
@@ -253,7 +284,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
 template <typename T, int NBAT, int TX, int TY>
 static size_t back3d_lds(const DevGeom &G, const LaunchCfg &L, int slot)
 {
-    size_t lds = sizeof(Rec<T>) * (size_t)TX * TY * L.rspan;
+    size_t lds = sizeof(AdjRec<T>) * (size_t)TX * TY * L.rspan;
     lds += sizeof(PlaneRow<T>) * (G.nv + 1);
     lds += sizeof(T) * (size_t)NBAT * L.back_pcols[slot] * (G.nv + 2);
     return lds;

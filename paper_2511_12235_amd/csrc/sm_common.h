@@ -76,6 +76,24 @@ struct alignas(16) Rec {
     alignas(16) T tab[MAXV][4];
 };
 
+// A strip record as the adjoint stages it in LDS (sm_back3d.hip): the fields
+// its terms read, and in place of the breakpoint table's first row (whose
+// depth and area are kept as d0 and A) the cubic coefficient g6[i] of Psi on
+// segment i, taken once from the table (see K_cut) instead of in every
+// straddle term.  seg[i] is table row i + 1, the far end of segment i; seg[4]
+// holds the farthest depth (later rows repeat the last breakpoint).  144
+// bytes in FP32 like the record, 272 in FP64.
+template <typename T>
+struct alignas(16) AdjRec {
+    double lc;
+    int n;
+    int unused_;
+    T kLo, kHi, cA, bA;
+    T d0, A;
+    T g6[MAXV - 1];
+    alignas(16) T seg[MAXV - 1][4];
+};
+
 // Stride of a strip record staged in LDS.  Lanes that gather different
 // records read the same field offset; a stride of a whole number of 128-byte
 // lines would put that field of every record in the same LDS bank, so such
@@ -502,6 +520,60 @@ __host__ __device__ inline T K_cut(const StripTab<T> &S, T tau, T inv_tau, T e)
     return tau < T(0) ? kp + e * S.A : kp;
 }
 
+// The adjoint's view of an AdjRec (uniform per record) and K_cut on it.
+template <typename T>
+struct AdjTab {
+    const T (*seg)[4];
+    const T *g6;
+    T d0, dn, A, b1, b2, b3, b4;  // nearest and farthest depth, area, interior breakpoints
+};
+
+template <typename T>
+__host__ __device__ inline AdjTab<T> adj_tab(const AdjRec<T> &R)
+{
+    AdjTab<T> S;
+    S.seg = R.seg;
+    S.g6 = R.g6;
+    S.d0 = R.d0;
+    S.dn = R.seg[MAXV - 2][0];
+    S.A = R.A;
+    S.b1 = R.seg[0][0];
+    S.b2 = R.seg[1][0];
+    S.b3 = R.seg[2][0];
+    S.b4 = R.seg[3][0];
+    return S;
+}
+
+// Clamp to [lo, hi] (lo <= hi): one median instruction in FP32 on the device.
+__host__ __device__ inline float clamp_(float v, float lo, float hi)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_fmed3f(v, lo, hi);
+#else
+    return v < lo ? lo : (v > hi ? hi : v);
+#endif
+}
+__host__ __device__ inline double clamp_(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
+
+// K_cut with the segment coefficients staged: the segment j holding lam as
+// in K_cut, then h = dB - lam with lam clamped to [d0, dn] first, which puts
+// h in [0, L] as K_cut's clamp does (below the nearest depth the first
+// segment is taken whole; beyond the farthest h = 0).
+template <typename T>
+__host__ __device__ inline T K_cut(const AdjTab<T> &S, T tau, T inv_tau, T e)
+{
+    const T lam = -e * inv_tau;
+    const int j = (int)(lam >= S.b1) + (int)(lam >= S.b2) + (int)(lam >= S.b3) + (int)(lam >= S.b4);
+    const T *r = S.seg[j];
+    const T dB = r[0], w1 = r[1], s0 = r[2], s1 = r[3];
+    const T h = dB - clamp_(lam, S.d0, S.dn);
+    T psi = fma(h, fma(h, fma(h, S.g6[j], w1), s0), s1);
+    const T below = S.d0 - lam;
+    psi += (below > T(0) ? below : T(0)) * S.A;
+    const T kp = fabs(tau) * psi;
+    return tau < T(0) ? kp + e * S.A : kp;
+}
+
 // The part of G_p of one plane for one strip record that needs no chord
 // table: the linear volume at face f = fa - 1 (the first voxel not wholly
 // below the plane).  Faces fa .. je are straddled (empty when je < fa); their
@@ -591,7 +663,7 @@ struct alignas(sizeof(T) == 4 ? 16 : 8) PlaneRow {
 // for the rare e - a > 2.  Every batch width takes the same steps, so that a
 // volume's result does not depend on the batch it is applied in.
 template <typename T, int NBAT>
-__host__ __device__ inline void adj_lin(const StripTab<T> &S, double lc, T cA, T bA, T kLo, T kHi,
+__host__ __device__ inline void adj_lin(const AdjTab<T> &S, double lc, T cA, T bA, T kLo, T kHi,
                                         const PlaneRow<T> *pl, double za, double zb, T v0dv, int nv,
                                         const T *Y, size_t ystride, int &pha, int &paa, int &phb,
                                         int &pab, T (&sum)[NBAT])
@@ -636,7 +708,7 @@ __host__ __device__ inline int adj_straddle(int t, int na, int pha, int phb, con
 // One strip record's contribution to voxel [za, zb] of its column in the
 // adjoint: sum_q (K_q(za) - K_q(zb)) (y[q-1] - y[q]) with y[-1] = y[nv] = 0.
 template <typename T, int NBAT>
-__host__ __device__ inline void adj_terms(const StripTab<T> &S, double lc, T cA, T bA, T kLo,
+__host__ __device__ inline void adj_terms(const AdjTab<T> &S, double lc, T cA, T bA, T kLo,
                                           T kHi, const PlaneRow<T> *pl,
                                           double za, double zb, T v0dv, int nv, const T *Y,
                                           size_t ystride, T (&sum)[NBAT])
