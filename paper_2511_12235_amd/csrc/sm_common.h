@@ -413,8 +413,6 @@ __host__ __device__ inline double clamp0(double v, double top) { return fmin(fma
 // device: clamp to [-1, top - 1] first (same result, and the conversion stays
 // in range), then one floor-and-convert instruction, which the compiler does
 // not form from floor and a conversion; three instructions instead of four.
-// (The forward's face splits use it; in the adjoint's plane splits the
-// opaque instruction cost the kernel 4 VGPRs and its 6 waves per SIMD.)
 __host__ __device__ inline int floor1_clamp(float v, float top)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -438,11 +436,8 @@ __host__ __device__ inline void plane_split(T z, T kLo, T kHi, T v0dv, int nv, i
     const T xh = z * (up ? kHi : kLo) - v0dv;  // hi(q) = z at this index
     const T xl = z * (up ? kLo : kHi) - v0dv;  // lo(q) = z at this index
     const T top = T(nv + 1);
-    T fh = floor(xh) + T(1), fl = ceil(xl);
-    fh = clamp0(fh, top);
-    fl = clamp0(fl, top);
-    ph = (int)fh;
-    pa = (int)fl;
+    ph = floor1_clamp(xh, top);
+    pa = (int)clamp0(T(ceil(xl)), top);
 }
 
 // Voxel faces z_j = z0 + j c against plane tau over the strip, whose nearest
@@ -672,17 +667,20 @@ __host__ __device__ inline void adj_lin(const AdjTab<T> &S, double lc, T cA, T b
     plane_split<T>(T(zb), kLo, kHi, v0dv, nv, phb, pab);
     const int n = pab - paa;      // >= 0: zb > za
     const int qa = min(paa, nv);  // a plane index even when n = 0 and a = nv + 1
-    T alpha = S.A * T(pl[qa].tau * lc - za);
-    alpha = n > 0 ? alpha : T(0);
+    const T alpha = S.A * T(pl[qa].tau * lc - za);
+    // Without selects: y[a-1] - y[e-1] is exactly 0 when n = 0 (a = e), and
+    // the first term of the second sum, read at min(a, e - 1), is exactly 0
+    // when n < 2; every index stays in [-1, nv].
+    const int q1 = min(paa, pab - 1);
 #pragma unroll
     for (int b = 0; b < NBAT; ++b) {
         const T *Yb = Y + b * ystride;
         const T ye = Yb[pab - 1];
-        T d = n >= 2 ? Yb[qa] - ye : T(0);
+        T d = Yb[q1] - ye;
         if (n >= 3) {  // rare: tested on n, the loop bounds only inside
             for (int q = paa + 1; q < pab - 1; ++q) d += Yb[q] - ye;
         }
-        sum[b] = fma(cA, ye, fma(alpha, Yb[qa - 1] - ye, bA * d));
+        sum[b] = fma(cA, ye, fma(alpha, Yb[paa - 1] - ye, bA * d));
     }
 }
 
