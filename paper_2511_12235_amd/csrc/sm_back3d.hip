@@ -93,7 +93,19 @@ __device__ __forceinline__ void stage_view(const DevGeom &G, const RecLayout &RL
                                      soff + strip * (RL.n_major_max + 1));
             }
         }
-        if (pos >= 0) {
+        // FP32 single volumes: a slot without a record, or with an empty
+        // polygon, gets a zero header.  kLo = kHi = 0 make both plane splits
+        // independent of the face, so that the record adds exactly zero (no
+        // linear volumes, no straddled planes whose table would be read,
+        // c A = A = 0) and the adjoint evaluates it without a test.  The
+        // other instances mark it n = 0 and skip it (the zero header cost
+        // them a wave per SIMD in registers).
+        constexpr bool kZeroEmpty = NBAT == 1 && sizeof(T) == 4;
+        if (kZeroEmpty && part == 0 && (pos < 0 || recs[strip * RL.cap + pos].n == 0)) {
+            dst->lc = 0.0;
+            dst->n = 0;
+            dst->kLo = dst->kHi = dst->cA = dst->bA = dst->d0 = dst->A = T(0);
+        } else if (pos >= 0) {
             const Rec<T> &src = recs[strip * RL.cap + pos];
             if (part == 0) {
                 dst->lc = src.lc;
@@ -245,9 +257,12 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
 #pragma unroll
             for (int b = 0; b < NBAT; ++b) cur[b] = acc[0][b];
             for (int k = max(k0, kmin); k <= k1; ++k) {
-                const AdjRec<T> &R = rtab[p * rspan + (k - k0)];  // LDS copy
-                const int n = __builtin_amdgcn_readfirstlane(R.n);
-                if (n == 0) continue;
+                const AdjRec<T> &R = rtab[p * rspan + (k - k0)];  // LDS copy (zeros when empty)
+                // FP32 single volumes evaluate an empty record (its zero
+                // header adds exactly zero), the others skip it
+                if constexpr (NBAT > 1 || sizeof(T) == 8) {
+                    if (__builtin_amdgcn_readfirstlane(R.n) == 0) continue;
+                }
                 const AdjTab<T> S = adj_tab<T>(R);
                 const T *Y = patch + (size_t)(k - kmin) * rowstride + 1;  // Y[-1] .. Y[nv]
                 T sum[NBAT];
