@@ -24,7 +24,7 @@
 
 namespace smk {
 
-static_assert(sizeof(AdjRec<float>) == 144 && sizeof(AdjRec<double>) == 272, "staged record");
+static_assert(sizeof(AdjRec<float>) == 160 && sizeof(AdjRec<double>) == 288, "staged record");
 
 // Stage view `view`'s detector columns kmin .. kmax (pc of them, all rows,
 // zero rows at -1 and nv) and the strip records of the tile's pixels, slot
@@ -94,7 +94,7 @@ __device__ __forceinline__ void stage_view(const DevGeom &G, const RecLayout &RL
             }
         }
         // FP32 single volumes: a slot without a record, or with an empty
-        // polygon, gets a zero header.  kLo = kHi = 0 make both plane splits
+        // polygon, gets a zero header.  Index scales 0 make both plane splits
         // independent of the face, so that the record adds exactly zero (no
         // linear volumes, no straddled planes whose table would be read,
         // c A = A = 0) and the adjoint evaluates it without a test.  The
@@ -104,14 +104,17 @@ __device__ __forceinline__ void stage_view(const DevGeom &G, const RecLayout &RL
         if (kZeroEmpty && part == 0 && (pos < 0 || recs[strip * RL.cap + pos].n == 0)) {
             dst->lc = 0.0;
             dst->n = 0;
-            dst->kLo = dst->kHi = dst->cA = dst->bA = dst->d0 = dst->A = T(0);
+            dst->k4[0] = dst->k4[1] = dst->k4[2] = dst->k4[3] = T(0);
+            dst->cA = dst->bA = dst->d0 = dst->A = T(0);
         } else if (pos >= 0) {
             const Rec<T> &src = recs[strip * RL.cap + pos];
             if (part == 0) {
                 dst->lc = src.lc;
                 dst->n = src.n;
-                dst->kLo = src.kLo;
-                dst->kHi = src.kHi;
+                dst->k4[0] = src.kLo;
+                dst->k4[1] = src.kHi;
+                dst->k4[2] = src.kHi;
+                dst->k4[3] = src.kLo;
                 dst->cA = src.cA;
                 dst->bA = src.bA;
                 dst->d0 = src.tab[0][0];
@@ -215,6 +218,8 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
     const double za = G.z0 + (double)iz * G.c;
     const double zb = G.z0 + (double)(iz + 1) * G.c;
     const T v0dv = T(G.v0 / G.dv);
+    // each face's index-scale pair in a staged record (see plane_split)
+    const int ka_off = T(za) >= T(0) ? 2 : 0, kb_off = T(zb) >= T(0) ? 2 : 0;
 
     T acc[TP][NBAT];
 #pragma unroll
@@ -266,7 +271,7 @@ back3d_kernel(DevGeom G, RecLayout RL, int v0, int nvc, const Rec<T> *__restrict
                 const AdjTab<T> S = adj_tab<T>(R);
                 const T *Y = patch + (size_t)(k - kmin) * rowstride + 1;  // Y[-1] .. Y[nv]
                 T sum[NBAT];
-                adj_terms<T, NBAT>(S, R.lc, R.cA, R.bA, R.kLo, R.kHi, prow, za, zb, v0dv,
+                adj_terms<T, NBAT>(S, R.lc, R.cA, R.bA, R.k4 + ka_off, R.k4 + kb_off, prow, za, zb, v0dv,
                                    nv, Y, (size_t)pcols * rowstride, sum);
 #pragma unroll
                 for (int b = 0; b < NBAT; ++b) cur[b] += sum[b];

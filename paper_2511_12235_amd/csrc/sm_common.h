@@ -81,15 +81,18 @@ struct alignas(16) Rec {
 // depth and area are kept as d0 and A) the cubic coefficient g6[i] of Psi on
 // segment i, taken once from the table (see K_cut) instead of in every
 // straddle term.  seg[i] is table row i + 1, the far end of segment i; seg[4]
-// holds the farthest depth (later rows repeat the last breakpoint).  144
-// bytes in FP32 like the record, 272 in FP64.
+// holds the farthest depth (later rows repeat the last breakpoint).  The
+// row-plane index scales are held in both orders, k4 = (kLo, kHi, kHi, kLo),
+// so that a lane reads the pair plane_split needs at a face of its sign
+// (k4 + 2 at z >= 0, k4 below) instead of selecting.  160 bytes in FP32,
+// 288 in FP64.
 template <typename T>
 struct alignas(16) AdjRec {
     double lc;
     int n;
     int unused_;
-    T kLo, kHi, cA, bA;
-    T d0, A;
+    T k4[4];
+    T cA, bA, d0, A;
     T g6[MAXV - 1];
     alignas(16) T seg[MAXV - 1][4];
 };
@@ -428,13 +431,14 @@ __host__ __device__ inline int floor1_clamp(float v, float top)
 __host__ __device__ inline int floor1_clamp(double v, double top) { return (int)clamp0(floor(v) + 1.0, top); }
 
 // Row planes: indices < ph lie wholly below z, indices >= pa wholly above.
-// tau_q = (v0 + q dv) / D, kLo = D / (Llo dv), kHi = D / (Lhi dv).
+// tau_q = (v0 + q dv) / D, kLo = D / (Llo dv), kHi = D / (Lhi dv); k is the
+// pair (kHi, kLo) for z >= 0 and (kLo, kHi) for z < 0 (plane q's highest
+// point over the strip is at the far depth when tau_q >= 0).
 template <typename T>
-__host__ __device__ inline void plane_split(T z, T kLo, T kHi, T v0dv, int nv, int &ph, int &pa)
+__host__ __device__ inline void plane_split(T z, const T *k, T v0dv, int nv, int &ph, int &pa)
 {
-    const bool up = z >= T(0);
-    const T xh = z * (up ? kHi : kLo) - v0dv;  // hi(q) = z at this index
-    const T xl = z * (up ? kLo : kHi) - v0dv;  // lo(q) = z at this index
+    const T xh = z * k[0] - v0dv;  // hi(q) = z at this index
+    const T xl = z * k[1] - v0dv;  // lo(q) = z at this index
     const T top = T(nv + 1);
     ph = floor1_clamp(xh, top);
     pa = (int)clamp0(T(ceil(xl)), top);
@@ -645,7 +649,7 @@ struct alignas(sizeof(T) == 4 ? 16 : 8) PlaneRow {
 // phb .. pab - 1 straddle zb (adj_straddle gives their terms).
 // Y[b * ystride + q] holds y[q] of batch element b for q in [-1, nv];
 // pl holds the plane slopes; cA = c A and bA = A lc dv / D come with the
-// record.
+// record, ka and kb are the index-scale pairs for za and zb (see plane_split).
 //
 // The linear volumes are K_q = A (tau_q lc - za) = alpha + (q - a) bA for
 // q = a .. e - 1 (a = paa, e = pab; the slopes tau_q are dv / D apart), with
@@ -658,13 +662,13 @@ struct alignas(sizeof(T) == 4 ? 16 : 8) PlaneRow {
 // for the rare e - a > 2.  Every batch width takes the same steps, so that a
 // volume's result does not depend on the batch it is applied in.
 template <typename T, int NBAT>
-__host__ __device__ inline void adj_lin(const AdjTab<T> &S, double lc, T cA, T bA, T kLo, T kHi,
+__host__ __device__ inline void adj_lin(const AdjTab<T> &S, double lc, T cA, T bA, const T *ka, const T *kb,
                                         const PlaneRow<T> *pl, double za, double zb, T v0dv, int nv,
                                         const T *Y, size_t ystride, int &pha, int &paa, int &phb,
                                         int &pab, T (&sum)[NBAT])
 {
-    plane_split<T>(T(za), kLo, kHi, v0dv, nv, pha, paa);
-    plane_split<T>(T(zb), kLo, kHi, v0dv, nv, phb, pab);
+    plane_split<T>(T(za), ka, v0dv, nv, pha, paa);
+    plane_split<T>(T(zb), kb, v0dv, nv, phb, pab);
     const int n = pab - paa;      // >= 0: zb > za
     const int qa = min(paa, nv);  // a plane index even when n = 0 and a = nv + 1
     const T alpha = S.A * T(pl[qa].tau * lc - za);
@@ -706,13 +710,13 @@ __host__ __device__ inline int adj_straddle(int t, int na, int pha, int phb, con
 // One strip record's contribution to voxel [za, zb] of its column in the
 // adjoint: sum_q (K_q(za) - K_q(zb)) (y[q-1] - y[q]) with y[-1] = y[nv] = 0.
 template <typename T, int NBAT>
-__host__ __device__ inline void adj_terms(const AdjTab<T> &S, double lc, T cA, T bA, T kLo,
-                                          T kHi, const PlaneRow<T> *pl,
+__host__ __device__ inline void adj_terms(const AdjTab<T> &S, double lc, T cA, T bA, const T *ka,
+                                          const T *kb, const PlaneRow<T> *pl,
                                           double za, double zb, T v0dv, int nv, const T *Y,
                                           size_t ystride, T (&sum)[NBAT])
 {
     int pha, paa, phb, pab;
-    adj_lin<T, NBAT>(S, lc, cA, bA, kLo, kHi, pl, za, zb, v0dv, nv, Y, ystride, pha, paa, phb,
+    adj_lin<T, NBAT>(S, lc, cA, bA, ka, kb, pl, za, zb, v0dv, nv, Y, ystride, pha, paa, phb,
                      pab, sum);
     const int na = max(paa - pha, 0);
     const int nb = max(pab - phb, 0);
