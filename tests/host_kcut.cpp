@@ -1,0 +1,113 @@
+// Host check of the adjoint's staged strip record (test helper, built and run
+// by tests/test_host_kcut.py; no GPU needed).
+//
+// The adjoint evaluates K (Sec. III-C: the volume of a strip column above a
+// face and below a row plane) on a staged copy of each strip record: the
+// cubic coefficient of Psi on every segment is taken once per record, and
+// lambda is clamped to [d0, dn] before h = dB - lambda.  The forward
+// evaluates it on the record itself: the coefficient per term, and h clamped
+// to [0, L].  This program builds the records of a small cone-beam scan with
+// build_record, converts each as the adjoint's staging does, and checks that
+// both forms give the same K bit for bit (host arithmetic) for face heights
+// that put lambda below the nearest depth, inside the table and beyond the
+// farthest depth, on rising, falling and level planes.
+#include "../paper_2511_12235_amd/csrc/sm_common.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+using namespace smk;
+
+template <typename T>
+static AdjRec<T> staged(const Rec<T> &R)
+{
+    AdjRec<T> A;
+    std::memset(&A, 0, sizeof A);
+    A.lc = R.lc;
+    A.n = R.n;
+    A.k4[0] = R.kLo;
+    A.k4[1] = R.kHi;
+    A.k4[2] = R.kHi;
+    A.k4[3] = R.kLo;
+    A.cA = R.cA;
+    A.bA = R.bA;
+    A.d0 = R.tab[0][0];
+    A.A = R.tab[0][2];
+    for (int r = 1; r < MAXV; ++r) {
+        for (int c = 0; c < 4; ++c) A.seg[r - 1][c] = R.tab[r][c];
+        const T L = R.tab[r][0] - R.tab[r - 1][0];
+        A.g6[r - 1] = (R.tab[r - 1][1] - R.tab[r][1]) * rcp_(L > T(1e-30) ? L : T(1e-30)) * T(1.0 / 3.0);
+    }
+    return A;
+}
+
+template <typename T>
+static long check(const DevGeom &G, long &checked)
+{
+    long bad = 0;
+    double2 scratch[8];
+    const int nview = 7;
+    const double angles[nview] = {0.0, 0.5 * M_PI, 0.3, 1.1, 2.0, 3.9, 5.5};
+    for (int v = 0; v < nview; ++v) {
+        const double cp = std::cos(angles[v]), sp = std::sin(angles[v]);
+        for (int iy = 0; iy < G.ny; ++iy)
+            for (int ix = 0; ix < G.nx; ++ix)
+                for (int k = 0; k < G.nu; ++k) {
+                    Rec<T> R;
+                    std::memset(&R, 0, sizeof R);
+                    build_record<T>(G, cp, sp, ix, iy, k, R, scratch);
+                    if (R.n == 0) continue;
+                    const AdjRec<T> A = staged(R);
+                    const StripTab<T> S = strip_tab<T>(R.tab, R.tab);
+                    const AdjTab<T> Q = adj_tab<T>(A);
+                    const T d0 = R.tab[0][0], dn = R.tab[MAXV - 1][0];
+                    for (int q = 0; q <= G.nv; ++q) {
+                        const T tau = T(G.tau[q]);
+                        const T inv = tau != T(0) ? T(1) / tau : T(0);
+                        for (int i = 0; i <= 40; ++i) {
+                            // lambda from below d0 to beyond dn
+                            const T lam = d0 - T(0.5) + (dn - d0 + T(1)) * T(i) / T(40);
+                            const T e = tau != T(0) ? -lam * tau : T(0.25) * T(i - 20);
+                            const T k1 = K_cut<T>(S, tau, inv, e), k2 = K_cut<T>(Q, tau, inv, e);
+                            ++checked;
+                            if (std::memcmp(&k1, &k2, sizeof(T)) != 0) {
+                                if (bad < 5)
+                                    std::printf("mismatch %s view %d pixel (%d,%d) column %d plane %d: %.17g %.17g\n",
+                                                sizeof(T) == 4 ? "fp32" : "fp64", v, ix, iy, k, q,
+                                                (double)k1, (double)k2);
+                                ++bad;
+                            }
+                        }
+                    }
+                }
+    }
+    return bad;
+}
+
+int main()
+{
+    // an 8 x 8 x 8 grid of unit voxels, source 30 from the centre, detector 60
+    // from the source, 12 columns and 8 rows of 1.5
+    DevGeom G;
+    std::memset(&G, 0, sizeof G);
+    G.dim = 3;
+    G.nx = G.ny = G.nz = 8;
+    G.n_p = 1;
+    G.nu = 12;
+    G.nv = 8;
+    G.a = G.b = G.c = 1.0;
+    G.x0 = G.y0 = G.z0 = -4.0;
+    G.s = 30.0;
+    G.D = 60.0;
+    G.du = G.dv = 1.5;
+    G.u0 = -0.5 * G.nu * G.du;
+    G.v0 = -0.5 * G.nv * G.dv;
+    double tau[9];
+    for (int q = 0; q <= G.nv; ++q) tau[q] = (G.v0 + q * G.dv) / G.D;
+    G.tau = tau;
+    long checked = 0;
+    const long bad = check<float>(G, checked) + check<double>(G, checked);
+    std::printf("checked %ld mismatches %ld\n", checked, bad);
+    return bad == 0 && checked > 0 ? 0 : 1;
+}
