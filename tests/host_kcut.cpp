@@ -10,7 +10,12 @@
 // build_record, converts each as the adjoint's staging does, and checks that
 // both forms give the same K bit for bit (host arithmetic) for face heights
 // that put lambda below the nearest depth, inside the table and beyond the
-// farthest depth, on rising, falling and level planes.
+// farthest depth, on rising, falling and level planes.  It also checks the
+// plane split the adjoint takes from the staged index-scale pairs (the pair
+// chosen by the sign of the face height) against each plane's height range
+// over the strip: planes put wholly below a face reach no higher than it,
+// planes put wholly above reach no lower, and every plane clear of the face
+// by more than rounding is put on its side.
 #include "../paper_2511_12235_amd/csrc/sm_common.h"
 
 #include <cmath>
@@ -85,6 +90,53 @@ static long check(const DevGeom &G, long &checked)
     return bad;
 }
 
+// Row planes q < ph must lie below face z and q >= pa above it (within tol),
+// and planes clear of z by more than tol must be classified so.
+template <typename T>
+static long check_splits(const DevGeom &G, long &checked)
+{
+    long bad = 0;
+    double2 scratch[8];
+    const double tol = sizeof(T) == 4 ? 1e-4 : 1e-9;
+    const double angles[4] = {0.0, 0.7, 2.3, 4.4};
+    for (int v = 0; v < 4; ++v) {
+        const double cp = std::cos(angles[v]), sp = std::sin(angles[v]);
+        for (int iy = 0; iy < G.ny; ++iy)
+            for (int ix = 0; ix < G.nx; ++ix)
+                for (int k = 0; k < G.nu; ++k) {
+                    Rec<T> R;
+                    std::memset(&R, 0, sizeof R);
+                    build_record<T>(G, cp, sp, ix, iy, k, R, scratch);
+                    if (R.n == 0) continue;
+                    const AdjRec<T> A = staged(R);
+                    const double Llo = R.lc + (double)R.tab[0][0], Lhi = R.lc + (double)R.tab[MAXV - 1][0];
+                    for (int j = 0; j <= G.nz; ++j) {
+                        const double z = G.z0 + j * G.c;
+                        const T zf = T(z);
+                        int ph, pa;
+                        plane_split<T>(zf, A.k4 + (zf >= T(0) ? 2 : 0), T(G.v0 / G.dv), G.nv, ph, pa);
+                        for (int q = 0; q <= G.nv; ++q) {
+                            const double t = G.tau[q];
+                            const double lo = t >= 0 ? t * Llo : t * Lhi, hi = t >= 0 ? t * Lhi : t * Llo;
+                            const bool below = q < ph, above = q >= pa;
+                            const bool ok = (!below || hi <= z + tol) && (!above || lo >= z - tol) &&
+                                            (!(hi < z - tol) || below) && (!(lo > z + tol) || above);
+                            ++checked;
+                            if (!ok) {
+                                if (bad < 5)
+                                    std::printf("split %s view %d pixel (%d,%d) column %d face %d plane %d: "
+                                                "ph %d pa %d range [%.9g, %.9g] z %.9g\n",
+                                                sizeof(T) == 4 ? "fp32" : "fp64", v, ix, iy, k, j, q, ph, pa,
+                                                lo, hi, z);
+                                ++bad;
+                            }
+                        }
+                    }
+                }
+    }
+    return bad;
+}
+
 int main()
 {
     // an 8 x 8 x 8 grid of unit voxels, source 30 from the centre, detector 60
@@ -106,8 +158,10 @@ int main()
     double tau[9];
     for (int q = 0; q <= G.nv; ++q) tau[q] = (G.v0 + q * G.dv) / G.D;
     G.tau = tau;
-    long checked = 0;
+    long checked = 0, checked_splits = 0;
     const long bad = check<float>(G, checked) + check<double>(G, checked);
-    std::printf("checked %ld mismatches %ld\n", checked, bad);
-    return bad == 0 && checked > 0 ? 0 : 1;
+    const long bad_splits = check_splits<float>(G, checked_splits) + check_splits<double>(G, checked_splits);
+    std::printf("splits checked %ld wrong %ld\n", checked_splits, bad_splits);
+    std::printf("checked %ld mismatches %ld\n", checked, bad + bad_splits);
+    return bad == 0 && bad_splits == 0 && checked > 0 && checked_splits > 0 ? 0 : 1;
 }

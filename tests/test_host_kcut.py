@@ -3,7 +3,10 @@ does (Sec. III-C): tests/host_kcut.cpp builds the records of a small cone-beam
 scan, converts each as the adjoint's staging does (segment coefficients taken
 once, lambda clamped to [d0, dn]) and compares K with the record's own form
 (coefficient per term, h clamped to [0, L]) bit for bit, in FP32 and FP64.
-Host arithmetic only: no GPU is used."""
+It also checks the row-plane split taken from the staged index-scale pairs
+against every plane's height range over the strip (Sec. III-C, the planes
+wholly below, straddling or wholly above a face).  Host arithmetic only: no
+GPU is used."""
 import os
 import shutil
 import subprocess
@@ -31,5 +34,7 @@ def test_staged_record_K_equals_record_K():
         r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
         print(r.stdout[-2000:])
         assert r.returncode == 0, r.stdout[-2000:]
-        last = r.stdout.strip().splitlines()[-1].split()
+        lines = r.stdout.strip().splitlines()
+        splits, last = lines[-2].split(), lines[-1].split()
+        assert splits[:2] == ["splits", "checked"] and int(splits[2]) > 10000 and splits[4] == "0"
         assert last[0] == "checked" and int(last[1]) > 100000 and last[3] == "0"
