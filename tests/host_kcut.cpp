@@ -15,7 +15,11 @@
 // chosen by the sign of the face height) against each plane's height range
 // over the strip: planes put wholly below a face reach no higher than it,
 // planes put wholly above reach no lower, and every plane clear of the face
-// by more than rounding is put on its side.
+// by more than rounding is put on its side.  Last, the adjoint's linear part
+// of a record (adj_lin: the planes reaching into a voxel from above its
+// bottom face summed by parts, with the absent terms read as exact zeros)
+// against the direct sum over those planes of A (tau_q lc - za) times
+// y[q-1] - y[q], plus c A y for the planes wholly above the voxel.
 #include "../paper_2511_12235_amd/csrc/sm_common.h"
 
 #include <cmath>
@@ -137,6 +141,67 @@ static long check_splits(const DevGeom &G, long &checked)
     return bad;
 }
 
+// adj_lin against the direct per-plane sum, random detector values.
+template <typename T>
+static long check_lin(const DevGeom &G, long &checked, long (&runs)[4])
+{
+    long bad = 0;
+    double2 scratch[8];
+    const double tol = sizeof(T) == 4 ? 2e-5 : 1e-12;
+    PlaneRow<T> pl[64];
+    for (int q = 0; q <= G.nv; ++q) {
+        pl[q].tau = G.tau[q];
+        pl[q].tf = T(G.tau[q]);
+        pl[q].inv = G.tau[q] != 0.0 ? T(1) / T(G.tau[q]) : T(0);
+    }
+    T ybuf[66];  // y[-1] .. y[nv], zero at both ends
+    unsigned rng = 12345u;
+    ybuf[0] = ybuf[G.nv + 1] = T(0);
+    for (int q = 0; q < G.nv; ++q) {
+        rng = rng * 1664525u + 1013904223u;
+        ybuf[q + 1] = T((rng >> 8) * (1.0 / 16777216.0) - 0.25);
+    }
+    const T *Y = ybuf + 1;
+    const double angles[3] = {0.2, 1.9, 3.6};
+    for (int v = 0; v < 3; ++v) {
+        const double cp = std::cos(angles[v]), sp = std::sin(angles[v]);
+        for (int iy = 0; iy < G.ny; ++iy)
+            for (int ix = 0; ix < G.nx; ++ix)
+                for (int k = 0; k < G.nu; ++k) {
+                    Rec<T> R;
+                    std::memset(&R, 0, sizeof R);
+                    build_record<T>(G, cp, sp, ix, iy, k, R, scratch);
+                    if (R.n == 0) continue;
+                    const AdjRec<T> A = staged(R);
+                    const AdjTab<T> S = adj_tab<T>(A);
+                    for (int iz = 0; iz < G.nz; ++iz) {
+                        const double za = G.z0 + iz * G.c, zb = G.z0 + (iz + 1) * G.c;
+                        int pha, paa, phb, pab;
+                        T sum[1];
+                        adj_lin<T, 1>(S, A.lc, A.cA, A.bA, A.k4 + (T(za) >= T(0) ? 2 : 0),
+                                      A.k4 + (T(zb) >= T(0) ? 2 : 0), pl, za, zb, T(G.v0 / G.dv), G.nv, Y,
+                                      0, pha, paa, phb, pab, sum);
+                        double ref = (double)A.cA * (double)Y[pab - 1], scale = std::fabs(ref);
+                        for (int q = paa; q < pab; ++q) {
+                            const double t = (double)A.A * (G.tau[q] * A.lc - za) * ((double)Y[q - 1] - (double)Y[q]);
+                            ref += t;
+                            scale += std::fabs(t);
+                        }
+                        ++checked;
+                        ++runs[pab - paa < 3 ? pab - paa : 3];
+                        if (!(std::fabs((double)sum[0] - ref) <= tol * (scale + 1e-30))) {
+                            if (bad < 5)
+                                std::printf("lin %s view %d pixel (%d,%d) column %d voxel %d planes %d..%d: %.17g %.17g\n",
+                                            sizeof(T) == 4 ? "fp32" : "fp64", v, ix, iy, k, iz, paa, pab,
+                                            (double)sum[0], ref);
+                            ++bad;
+                        }
+                    }
+                }
+    }
+    return bad;
+}
+
 int main()
 {
     // an 8 x 8 x 8 grid of unit voxels, source 30 from the centre, detector 60
@@ -161,7 +226,25 @@ int main()
     long checked = 0, checked_splits = 0;
     const long bad = check<float>(G, checked) + check<double>(G, checked);
     const long bad_splits = check_splits<float>(G, checked_splits) + check_splits<double>(G, checked_splits);
+    // the linear parts also on rows of a third of a voxel's projection, so
+    // that voxels hold three or more planes (the by-parts form's loop)
+    DevGeom F = G;
+    F.nv = 24;
+    F.dv = 0.5;
+    F.v0 = -0.5 * F.nv * F.dv;
+    double tauf[25];
+    for (int q = 0; q <= F.nv; ++q) tauf[q] = (F.v0 + q * F.dv) / F.D;
+    F.tau = tauf;
+    long checked_lin = 0, runs[4] = {0, 0, 0, 0};
+    const long bad_lin = check_lin<float>(G, checked_lin, runs) + check_lin<double>(G, checked_lin, runs) +
+                         check_lin<float>(F, checked_lin, runs) + check_lin<double>(F, checked_lin, runs);
+    std::printf("linear parts checked %ld wrong %ld (planes per voxel 0: %ld, 1: %ld, 2: %ld, 3+: %ld)\n",
+                checked_lin, bad_lin, runs[0], runs[1], runs[2], runs[3]);
+    for (int i = 0; i < 4; ++i)
+        if (runs[i] == 0) return 1;
     std::printf("splits checked %ld wrong %ld\n", checked_splits, bad_splits);
-    std::printf("checked %ld mismatches %ld\n", checked, bad + bad_splits);
-    return bad == 0 && bad_splits == 0 && checked > 0 && checked_splits > 0 ? 0 : 1;
+    std::printf("checked %ld mismatches %ld\n", checked, bad + bad_splits + bad_lin);
+    return bad == 0 && bad_splits == 0 && bad_lin == 0 && checked > 0 && checked_splits > 0 && checked_lin > 0
+               ? 0
+               : 1;
 }

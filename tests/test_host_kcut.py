@@ -5,8 +5,10 @@ once, lambda clamped to [d0, dn]) and compares K with the record's own form
 (coefficient per term, h clamped to [0, L]) bit for bit, in FP32 and FP64.
 It also checks the row-plane split taken from the staged index-scale pairs
 against every plane's height range over the strip (Sec. III-C, the planes
-wholly below, straddling or wholly above a face).  Host arithmetic only: no
-GPU is used."""
+wholly below, straddling or wholly above a face), and the adjoint's linear
+part of a record (the planes reaching into a voxel from above its bottom
+face, summed by parts) against the direct per-plane sum, for voxels holding
+0, 1, 2 and 3 or more such planes.  Host arithmetic only: no GPU is used."""
 import os
 import shutil
 import subprocess
@@ -35,6 +37,7 @@ def test_staged_record_K_equals_record_K():
         print(r.stdout[-2000:])
         assert r.returncode == 0, r.stdout[-2000:]
         lines = r.stdout.strip().splitlines()
-        splits, last = lines[-2].split(), lines[-1].split()
+        lin, splits, last = lines[-3].split(), lines[-2].split(), lines[-1].split()
+        assert lin[:3] == ["linear", "parts", "checked"] and int(lin[3]) > 1000 and lin[5] == "0"
         assert splits[:2] == ["splits", "checked"] and int(splits[2]) > 10000 and splits[4] == "0"
         assert last[0] == "checked" and int(last[1]) > 100000 and last[3] == "0"
