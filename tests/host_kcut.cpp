@@ -19,7 +19,10 @@
 // of a record (adj_lin: the planes reaching into a voxel from above its
 // bottom face summed by parts, with the absent terms read as exact zeros)
 // against the direct sum over those planes of A (tau_q lc - za) times
-// y[q-1] - y[q], plus c A y for the planes wholly above the voxel.
+// y[q-1] - y[q], plus c A y for the planes wholly above the voxel.  And the
+// zero header an empty slot gets in FP32 single-volume launches: its terms
+// (adj_terms) are exactly zero for every voxel, without reading the table
+// (filled with NaN here).
 #include "../paper_2511_12235_amd/csrc/sm_common.h"
 
 #include <cmath>
@@ -202,6 +205,44 @@ static long check_lin(const DevGeom &G, long &checked, long (&runs)[4])
     return bad;
 }
 
+// A staged slot with a zero header adds exactly zero and reads no table row.
+template <typename T>
+static long check_zero(const DevGeom &G, long &checked)
+{
+    long bad = 0;
+    PlaneRow<T> pl[64];
+    for (int q = 0; q <= G.nv; ++q) {
+        pl[q].tau = G.tau[q];
+        pl[q].tf = T(G.tau[q]);
+        pl[q].inv = G.tau[q] != 0.0 ? T(1) / T(G.tau[q]) : T(0);
+    }
+    T ybuf[66];
+    ybuf[0] = ybuf[G.nv + 1] = T(0);
+    for (int q = 0; q < G.nv; ++q) ybuf[q + 1] = T(0.5) + T(q);
+    AdjRec<T> Z;
+    std::memset(&Z, 0, sizeof Z);
+    const T nan = std::nan("");
+    for (int i = 0; i < MAXV - 1; ++i) {
+        Z.g6[i] = nan;
+        for (int c = 0; c < 4; ++c) Z.seg[i][c] = nan;
+    }
+    const AdjTab<T> S = adj_tab<T>(Z);
+    for (int iz = 0; iz < G.nz; ++iz) {
+        const double za = G.z0 + iz * G.c, zb = G.z0 + (iz + 1) * G.c;
+        T sum[1];
+        adj_terms<T, 1>(S, Z.lc, Z.cA, Z.bA, Z.k4 + (T(za) >= T(0) ? 2 : 0), Z.k4 + (T(zb) >= T(0) ? 2 : 0),
+                        pl, za, zb, T(G.v0 / G.dv), G.nv, ybuf + 1, 0, sum);
+        ++checked;
+        if (!(sum[0] == T(0))) {
+            if (bad < 5)
+                std::printf("zero header %s voxel %d: %.17g\n", sizeof(T) == 4 ? "fp32" : "fp64", iz,
+                            (double)sum[0]);
+            ++bad;
+        }
+    }
+    return bad;
+}
+
 int main()
 {
     // an 8 x 8 x 8 grid of unit voxels, source 30 from the centre, detector 60
@@ -242,6 +283,11 @@ int main()
                 checked_lin, bad_lin, runs[0], runs[1], runs[2], runs[3]);
     for (int i = 0; i < 4; ++i)
         if (runs[i] == 0) return 1;
+    long checked_zero = 0;
+    const long bad_zero = check_zero<float>(G, checked_zero) + check_zero<double>(G, checked_zero) +
+                          check_zero<float>(F, checked_zero) + check_zero<double>(F, checked_zero);
+    std::printf("zero headers checked %ld nonzero %ld\n", checked_zero, bad_zero);
+    if (bad_zero != 0 || checked_zero == 0) return 1;
     std::printf("splits checked %ld wrong %ld\n", checked_splits, bad_splits);
     std::printf("checked %ld mismatches %ld\n", checked, bad + bad_splits + bad_lin);
     return bad == 0 && bad_splits == 0 && bad_lin == 0 && checked > 0 && checked_splits > 0 && checked_lin > 0

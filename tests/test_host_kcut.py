@@ -8,7 +8,9 @@ against every plane's height range over the strip (Sec. III-C, the planes
 wholly below, straddling or wholly above a face), and the adjoint's linear
 part of a record (the planes reaching into a voxel from above its bottom
 face, summed by parts) against the direct per-plane sum, for voxels holding
-0, 1, 2 and 3 or more such planes.  Host arithmetic only: no GPU is used."""
+0, 1, 2 and 3 or more such planes, and that the zero header of an empty
+slot adds exactly zero without reading the table.  Host arithmetic only: no
+GPU is used."""
 import os
 import shutil
 import subprocess
@@ -36,8 +38,12 @@ def test_staged_record_K_equals_record_K():
         r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
         print(r.stdout[-2000:])
         assert r.returncode == 0, r.stdout[-2000:]
-        lines = r.stdout.strip().splitlines()
-        lin, splits, last = lines[-3].split(), lines[-2].split(), lines[-1].split()
-        assert lin[:3] == ["linear", "parts", "checked"] and int(lin[3]) > 1000 and lin[5] == "0"
-        assert splits[:2] == ["splits", "checked"] and int(splits[2]) > 10000 and splits[4] == "0"
-        assert last[0] == "checked" and int(last[1]) > 100000 and last[3] == "0"
+        lines = {" ".join(l.split()[:2]): l.split() for l in r.stdout.strip().splitlines()}
+        lin = lines["linear parts"]
+        assert int(lin[3]) > 1000 and lin[5] == "0"
+        zero = lines["zero headers"]
+        assert int(zero[3]) > 0 and zero[5] == "0"
+        splits = lines["splits checked"]
+        assert int(splits[2]) > 10000 and splits[4] == "0"
+        last = lines["checked " + r.stdout.strip().splitlines()[-1].split()[1]]
+        assert int(last[1]) > 100000 and last[3] == "0"
